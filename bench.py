@@ -1,0 +1,262 @@
+"""Benchmark: gate throughput of the HIP state-vector engine on one MI355X.
+
+Primary workload (the `value`): a 30-qubit complex128 layered circuit --
+20 layers, each a Haar-random 1-qubit gate on every qubit followed by CNOTs
+on the even then the odd nearest-neighbour pairs (1180 gates), seeded and
+synthetic.  One step = init |0...0> + the whole circuit (fused tile passes)
++ norm + <Z_0 Z_29>.  value = gates / second over the timed steps.
+
+Also reported (same JSON line):
+  roofline      achieved HBM GB/s of the dominant kernel (fused tile pass),
+                from HIP events on the library's stream over the timed steps
+  cpu_baseline  the FP64 CPU oracle on the same 30-qubit circuit, first gates
+                only (time-bounded sample), on this host's cores
+  extras        complex64 throughput of the same circuit; unfused per-gate
+                kernel bandwidth; adjoint-gradient / forward time ratio on a
+                24-qubit ansatz (10 layers RY,RZ + CZ ring, 480 parameters)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "gates/s + HBM GB/s (% peak) at 30 qubits; adjoint-grad time / forward time"
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20, seed: int = 3002):
+    import torch
+    c = W.layered_cnot_brick(n, layers, seed)
+    g = q.marshal_gates(c.gates)
+    ctx = q.Context()
+    st = q.State(ctx, n, dtype)
+    obs = c.observable
+
+    def step():
+        st.init_basis(0)
+        st.apply_circuit(None, marshalled=g)
+        st.norm2()
+        return st.expect_z(obs)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        terms, _ = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    norm = st.norm2()
+    st.free()
+    del st
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"gates": len(c.gates), "seconds": t1 - t0, "prof": prof, "norm": norm,
+            "zz": float(terms[0])}
+
+
+def kernel_roofline(prof: dict, name: str):
+    k = prof.get(name)
+    if not k or k["launches"] == 0 or k["ms"] <= 0:
+        return None
+    per_launch_bytes = k["bytes"] / k["launches"]
+    avg_s = k["ms"] / k["launches"] / 1e3
+    achieved = per_launch_bytes / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": name, "launches": k["launches"], "avg_ms": round(k["ms"] / k["launches"], 4),
+            "bytes_per_launch": per_launch_bytes}
+
+
+def unfused_sweep(q, W, n: int):
+    """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(3003)
+    gates = []
+    for qb in range(n):
+        gates.append(W.g1(qb, W.haar_unitary(2, rng)))
+    for qb in range(0, n - 1, 3):
+        gates.append(W.gc(qb, qb + 1, W.haar_unitary(2, rng)))
+        gates.append(W.g2(qb, n - 1 - qb if n - 1 - qb != qb else qb + 1, W.haar_unitary(4, rng)))
+    g = q.marshal_gates(gates)
+    ctx = q.Context()
+    st = q.State(ctx, n, q.QSV_C128)
+    st.init_basis(0)
+    st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+    prof = ctx.profile_end()
+    st.free()
+    del st
+    ctx.close()
+    torch.cuda.empty_cache()
+    out = {}
+    for k, v in prof.items():
+        out[k] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                  "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
+    return out
+
+
+def adjoint_ratio(q, W, n: int = 24, layers: int = 10, dtype=None, reps: int = 3):
+    import torch
+    dtype = q.QSV_C128 if dtype is None else dtype
+    c = W.hea_cz_ring(n, layers, seed=1005)
+    g = q.marshal_gates(c.gates)
+    ctx = q.Context()
+    psi, lam = q.State(ctx, n, dtype), q.State(ctx, n, dtype)
+
+    def forward():
+        psi.init_basis(0)
+        psi.apply_circuit(None, c.params, marshalled=g)
+        return psi.expect_z(c.observable)[1]
+
+    def backward():
+        return q.adjoint(psi, lam, None, c.params, c.observable, flags=0, marshalled=g)
+
+    forward()
+    backward()
+    tf, tb = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    psi.free()
+    lam.free()
+    ctx.close()
+    tf, tb = min(tf), min(tb)
+    return {"workload": f"hea_cz_ring n={n} layers={layers} params={len(c.params)}",
+            "forward_ms": round(tf * 1e3, 3), "adjoint_ms": round(tb * 1e3, 3),
+            "adjoint_over_forward": round(tb / tf, 3)}
+
+
+def cpu_baseline(W, n: int, budget_s: float = 15.0):
+    import numpy as np
+    import oracle as O
+    c = W.layered_cnot_brick(n, 20, 3002)
+    s = np.zeros(2 ** n, dtype=np.complex128)
+    s[0] = 1.0
+    work = np.zeros_like(s)
+    L = O.lib()
+    gates = O.marshal(c)
+    p = np.zeros(1)
+    done = 0
+    t_total = 0.0
+    ptr = lambda a: a.ctypes.data_as(O.ctypes.c_void_p)  # noqa: E731
+    # warm the pages of both buffers with one untimed gate
+    L.orc_run(n, ptr(s), ptr(work), 1, ptr(gates[0:1]), ptr(p))
+    k = 1
+    while t_total < budget_s and k < len(gates):
+        t0 = time.perf_counter()
+        L.orc_run(n, ptr(s), ptr(work), 1, ptr(gates[k:k + 1]), ptr(p))
+        t_total += time.perf_counter() - t0
+        done += 1
+        k += 1
+        log(f"cpu oracle gate {k}/{len(gates)}: {t_total:.1f} s")
+    return {"value": round(done / t_total, 4), "unit": "gates/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"gates 2..{k} of the same {n}-qubit 1180-gate circuit, FP64 oracle "
+                      f"(out-of-place Kronecker-definition loops, OpenMP), {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device copy of 2^k complex128 amplitudes (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device"}))
+        sys.exit(1)
+    import paper_2303_00123_amd as q
+    import workloads as W
+
+    if args.copy_probe:
+        a = torch.empty(2 ** args.copy_probe, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 16, "copies": 3}))
+        return
+
+    log(f"primary: n={args.n} c128 steps={args.steps} warmup={args.warmup}")
+    r = primary(q, W, args.n, q.QSV_C128, args.steps, args.warmup)
+    value = r["gates"] * args.steps / r["seconds"]
+    roof = kernel_roofline(r["prof"], "tile_pass_c128")
+    log(f"primary: {value:.1f} gates/s, roofline {roof}")
+    extras = {"norm_after": r["norm"], "zz_0_last": r["zz"],
+              "kernels_c128": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
+                               for k, v in r["prof"].items()}}
+    if not args.no_extras:
+        log("extras: complex64")
+        r64 = primary(q, W, args.n, q.QSV_C64, max(2, args.steps // 2), 1)
+        extras["c64"] = {"gates_per_s": round(r64["gates"] * max(2, args.steps // 2) / r64["seconds"], 2),
+                         "roofline": kernel_roofline(r64["prof"], "tile_pass_c64")}
+        log("extras: unfused sweep")
+        extras["unfused_c128"] = unfused_sweep(q, W, args.n)
+        log("extras: adjoint ratio")
+        extras["adjoint"] = adjoint_ratio(q, W)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(W, args.n)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["seconds"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"layered CNOT-brick circuit, {args.n} qubits, 20 layers "
+                               f"({r['gates']} gates: Haar 1q on every qubit + CNOT even/odd "
+                               f"pairs), complex128, seed 3002; step = init + circuit + norm "
+                               f"+ <Z0 Z{args.n - 1}>",
+                   "n_qubits": args.n, "gates": r["gates"], "state_bytes": 16 * 2 ** args.n},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,687 @@
+// C ABI entry points: argument validation, lowering of gates to index-bit
+// positions, dispatch to the HIP launchers, error mapping.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+
+#include "qsv_internal.h"
+
+using namespace qsv;
+
+namespace {
+
+qsv_status fail(qsv_ctx ctx, qsv_status st, const std::string& msg) {
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+qsv_status hip_fail(qsv_ctx ctx, hipError_t e, const char* where) {
+    std::string msg = std::string(where) + ": " + hipGetErrorName(e) + " (" +
+                      hipGetErrorString(e) + ")";
+    return fail(ctx, e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP, msg);
+}
+
+#define HIP_OR_FAIL(ctx, expr, where)                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+bool valid_dtype(int d) { return d == QSV_C64 || d == QSV_C128; }
+
+qsv_status check_device(qsv_ctx ctx) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device)
+        return fail(ctx, QSV_ERR_ARG, "the context's device is not the current HIP device");
+    return QSV_OK;
+}
+
+qsv_status check_state(qsv_state st) {
+    if (!st || !st->ctx) return QSV_ERR_ARG;
+    return check_device(st->ctx);
+}
+
+inline int pos_of(int n, int q) { return n - 1 - q; }
+
+// 2x2 rotation exp(-i theta P / 2) = cos(theta/2) I - i sin(theta/2) P
+void rotation_matrix(int axis, double theta, double* m) {
+    const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
+    for (int i = 0; i < 8; ++i) m[i] = 0.0;
+    switch (axis) {
+    case QSV_AXIS_X:  // [[c, -i s], [-i s, c]]
+        m[0] = c; m[3] = -s; m[5] = -s; m[6] = c;
+        break;
+    case QSV_AXIS_Y:  // [[c, -s], [s, c]]
+        m[0] = c; m[2] = -s; m[4] = s; m[6] = c;
+        break;
+    default:          // Z: diag(c - i s, c + i s)
+        m[0] = c; m[1] = -s; m[6] = c; m[7] = s;
+        break;
+    }
+}
+
+// Validate and lower gates to index-bit positions; rotations become G1Q.
+qsv_status lower(qsv_ctx ctx, int n, const qsv_gate* g, int64_t ng, const double* params,
+                 int64_t nparams, std::vector<PGate>& out, bool dagger = false) {
+    out.clear();
+    out.reserve(size_t(ng));
+    for (int64_t i = 0; i < ng; ++i) {
+        const qsv_gate& G = g[i];
+        PGate p{};
+        const std::string at = "gate " + std::to_string(i) + ": ";
+        switch (G.kind) {
+        case QSV_G1Q:
+        case QSV_GROT:
+            if (G.q0 < 0 || G.q0 >= n) return fail(ctx, QSV_ERR_QUBIT, at + "qubit out of range");
+            p.kind = QSV_G1Q;
+            p.p0 = pos_of(n, G.q0);
+            if (G.kind == QSV_GROT) {
+                if (G.axis < 0 || G.axis > 2) return fail(ctx, QSV_ERR_ARG, at + "bad rotation axis");
+                if (G.param < 0 || G.param >= nparams || !params)
+                    return fail(ctx, QSV_ERR_ARG, at + "rotation parameter index out of range");
+                rotation_matrix(G.axis, params[G.param], p.m);
+            } else {
+                std::memcpy(p.m, G.m, 8 * sizeof(double));
+            }
+            break;
+        case QSV_GC1Q:
+            if (n < 2) return fail(ctx, QSV_ERR_QUBIT, at + "controlled gate needs n >= 2");
+            if (G.q0 < 0 || G.q0 >= n || G.q1 < 0 || G.q1 >= n)
+                return fail(ctx, QSV_ERR_QUBIT, at + "qubit out of range");
+            if (G.q0 == G.q1) return fail(ctx, QSV_ERR_QUBIT, at + "control equals target");
+            if (G.ctrl_state != 0 && G.ctrl_state != 1)
+                return fail(ctx, QSV_ERR_ARG, at + "control state must be 0 or 1");
+            p.kind = QSV_GC1Q;
+            p.p0 = pos_of(n, G.q0);
+            p.p1 = pos_of(n, G.q1);
+            p.cs = G.ctrl_state;
+            std::memcpy(p.m, G.m, 8 * sizeof(double));
+            break;
+        case QSV_G2Q:
+            if (n < 2) return fail(ctx, QSV_ERR_QUBIT, at + "2-qubit gate needs n >= 2");
+            if (G.q0 < 0 || G.q0 >= n || G.q1 < 0 || G.q1 >= n)
+                return fail(ctx, QSV_ERR_QUBIT, at + "qubit out of range");
+            if (G.q0 == G.q1) return fail(ctx, QSV_ERR_QUBIT, at + "repeated qubit");
+            p.kind = QSV_G2Q;
+            p.p0 = pos_of(n, G.q0);
+            p.p1 = pos_of(n, G.q1);
+            std::memcpy(p.m, G.m, 32 * sizeof(double));
+            break;
+        default:
+            return fail(ctx, QSV_ERR_ARG, at + "unknown gate kind");
+        }
+        if (dagger) {  // conjugate transpose
+            const int d = p.kind == QSV_G2Q ? 4 : 2;
+            double t[32];
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c) {
+                    t[2 * (r * d + c)] = p.m[2 * (c * d + r)];
+                    t[2 * (r * d + c) + 1] = -p.m[2 * (c * d + r) + 1];
+                }
+            std::memcpy(p.m, t, sizeof(double) * 2 * d * d);
+        }
+        out.push_back(p);
+    }
+    return QSV_OK;
+}
+
+}  // namespace
+
+namespace qsv {
+
+hipError_t plan_staging(qsv_ctx ctx, size_t bytes, void** host) {
+    hipError_t e = hipEventSynchronize(ctx->plan_copied);   // previous upload has left h_plan
+    if (e != hipSuccess) return e;
+    if (bytes > ctx->h_plan_bytes) {
+        if (ctx->h_plan) hipHostFree(ctx->h_plan);
+        ctx->h_plan = nullptr;
+        ctx->h_plan_bytes = 0;
+        size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes * 2;
+        e = hipHostMalloc(&ctx->h_plan, want, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        ctx->h_plan_bytes = want;
+    }
+    *host = ctx->h_plan;
+    return hipSuccess;
+}
+
+hipError_t plan_upload(qsv_ctx ctx, size_t bytes, void** dev) {
+    hipError_t e;
+    if (bytes > ctx->d_plan_bytes) {
+        e = hipStreamSynchronize(ctx->stream);   // older passes may still read d_plan
+        if (e != hipSuccess) return e;
+        if (ctx->d_plan) hipFree(ctx->d_plan);
+        ctx->d_plan = nullptr;
+        ctx->d_plan_bytes = 0;
+        size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes * 2;
+        e = hipMalloc(&ctx->d_plan, want);
+        if (e != hipSuccess) return e;
+        ctx->d_plan_bytes = want;
+    }
+    e = hipMemcpyAsync(ctx->d_plan, ctx->h_plan, bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ctx->plan_copied, ctx->stream);
+    if (e != hipSuccess) return e;
+    *dev = ctx->d_plan;
+    return hipSuccess;
+}
+
+hipError_t ensure_aux(qsv_ctx ctx, size_t doubles) {
+    if (doubles <= ctx->d_aux_doubles) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    if (ctx->d_aux) hipFree(ctx->d_aux);
+    ctx->d_aux = nullptr;
+    ctx->d_aux_doubles = 0;
+    size_t want = doubles < 65536 ? 65536 : doubles * 2;
+    e = hipMalloc(reinterpret_cast<void**>(&ctx->d_aux), want * sizeof(double));
+    if (e != hipSuccess) return e;
+    ctx->d_aux_doubles = want;
+    return hipSuccess;
+}
+
+static hipEvent_t pool_event(qsv_ctx ctx) {
+    if (ctx->event_next == ctx->event_pool.size()) {
+        hipEvent_t ev = nullptr;
+        if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+        ctx->event_pool.push_back(ev);
+    }
+    return ctx->event_pool[ctx->event_next++];
+}
+
+void prof_before(qsv_ctx ctx, const char* name, double bytes) {
+    if (!ctx->profiling) return;
+    ProfRec r{name, bytes, pool_event(ctx), pool_event(ctx)};
+    if (!r.start || !r.stop) return;
+    hipEventRecord(r.start, ctx->stream);
+    ctx->prof.push_back(r);
+}
+
+void prof_after(qsv_ctx ctx) {
+    if (!ctx->profiling || ctx->prof.empty()) return;
+    hipEventRecord(ctx->prof.back().stop, ctx->stream);
+}
+
+}  // namespace qsv
+
+extern "C" {
+
+const char* qsv_status_str(qsv_status s) {
+    switch (s) {
+    case QSV_OK: return "ok";
+    case QSV_ERR_ARG: return "invalid argument";
+    case QSV_ERR_QUBIT: return "invalid qubit index";
+    case QSV_ERR_NOMEM: return "out of memory";
+    case QSV_ERR_HIP: return "HIP runtime error";
+    case QSV_ERR_DTYPE: return "invalid or mismatched dtype";
+    case QSV_ERR_ALIGN: return "misaligned device pointer";
+    case QSV_ERR_SIZE: return "invalid size";
+    default: return "unknown status";
+    }
+}
+
+const char* qsv_last_error(qsv_ctx ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+qsv_status qsv_ctx_create(void* hip_stream, qsv_ctx* out) {
+    if (!out) return QSV_ERR_ARG;
+    *out = nullptr;
+    qsv_ctx ctx = new (std::nothrow) qsv_ctx_s();
+    if (!ctx) return QSV_ERR_NOMEM;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e == hipSuccess) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
+                hipSuccess && cus > 0)
+            ctx->num_cus = cus;
+        e = hipMalloc(reinterpret_cast<void**>(&ctx->d_red), kRedDoubles * sizeof(double));
+    }
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_red), 4096, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->plan_copied, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ctx->plan_copied, ctx->stream);
+    if (e != hipSuccess) {
+        qsv_status st = e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP;
+        qsv_ctx_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return QSV_OK;
+}
+
+qsv_status qsv_ctx_set_stream(qsv_ctx ctx, void* hip_stream) {
+    if (!ctx) return QSV_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (s == ctx->stream) return QSV_OK;
+    // order the old stream's outstanding work before anything on the new one
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->stream = s;
+    return QSV_OK;
+}
+
+qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
+    if (!ctx) return QSV_ERR_ARG;
+    if (ctx->stream || ctx->d_red) hipStreamSynchronize(ctx->stream);
+    if (ctx->d_red) hipFree(ctx->d_red);
+    if (ctx->h_red) hipHostFree(ctx->h_red);
+    if (ctx->d_plan) hipFree(ctx->d_plan);
+    if (ctx->d_aux) hipFree(ctx->d_aux);
+    if (ctx->h_plan) hipHostFree(ctx->h_plan);
+    if (ctx->plan_copied) hipEventDestroy(ctx->plan_copied);
+    for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
+    if (ctx->batch_graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
+    if (ctx->d_batch) hipFree(ctx->d_batch);
+    delete ctx;
+    return QSV_OK;
+}
+
+qsv_status qsv_sync(qsv_ctx ctx) {
+    if (!ctx) return QSV_ERR_ARG;
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return QSV_OK;
+}
+
+// ------------------------------------------------------------------ states
+static qsv_status check_n(qsv_ctx ctx, int n) {
+    if (n < 1 || n > kMaxQubits)
+        return fail(ctx, QSV_ERR_SIZE, "n must be in [1, " + std::to_string(kMaxQubits) + "]");
+    return QSV_OK;
+}
+
+qsv_status qsv_state_wrap(qsv_ctx ctx, void* dev_ptr, size_t nbytes, int n, int dtype,
+                          qsv_state* out) {
+    if (!ctx || !out) return QSV_ERR_ARG;
+    *out = nullptr;
+    if (!dev_ptr) return fail(ctx, QSV_ERR_ARG, "null device pointer");
+    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+    if (qsv_status st = check_n(ctx, n)) return st;
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 16)
+        return fail(ctx, QSV_ERR_ALIGN, "device pointer must be 16-byte aligned");
+    const size_t need = (size_t(1) << n) * amp_bytes(dtype);
+    if (nbytes < need)
+        return fail(ctx, QSV_ERR_SIZE, "buffer holds " + std::to_string(nbytes) + " bytes, need " +
+                                           std::to_string(need));
+    qsv_state st = new (std::nothrow) qsv_state_s();
+    if (!st) return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
+    st->ctx = ctx;
+    st->ptr = dev_ptr;
+    st->n = n;
+    st->dtype = dtype;
+    st->owns = false;
+    st->nbytes = nbytes;
+    *out = st;
+    return QSV_OK;
+}
+
+qsv_status qsv_state_alloc(qsv_ctx ctx, int n, int dtype, qsv_state* out) {
+    if (!ctx || !out) return QSV_ERR_ARG;
+    *out = nullptr;
+    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+    if (qsv_status st = check_n(ctx, n)) return st;
+    if (qsv_status st = check_device(ctx)) return st;
+    const size_t need = (size_t(1) << n) * amp_bytes(dtype);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, QSV_ERR_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    qsv_state st = new (std::nothrow) qsv_state_s();
+    if (!st) {
+        hipFree(p);
+        return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
+    }
+    st->ctx = ctx;
+    st->ptr = p;
+    st->n = n;
+    st->dtype = dtype;
+    st->owns = true;
+    st->nbytes = need;
+    *out = st;
+    return QSV_OK;
+}
+
+qsv_status qsv_state_free(qsv_state st) {
+    if (!st) return QSV_ERR_ARG;
+    if (st->owns && st->ptr) {
+        hipStreamSynchronize(st->ctx->stream);
+        hipFree(st->ptr);
+    }
+    delete st;
+    return QSV_OK;
+}
+
+qsv_status qsv_state_info(qsv_state st, int* n, int* dtype, void** dev_ptr) {
+    if (!st) return QSV_ERR_ARG;
+    if (n) *n = st->n;
+    if (dtype) *dtype = st->dtype;
+    if (dev_ptr) *dev_ptr = st->ptr;
+    return QSV_OK;
+}
+
+qsv_status qsv_init_basis(qsv_state st, uint64_t b) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (b >= (uint64_t(1) << st->n)) return fail(ctx, QSV_ERR_ARG, "basis index >= 2^n");
+    HIP_OR_FAIL(ctx, launch_init_basis(ctx, st->ptr, st->n, st->dtype, b), "init_basis");
+    return QSV_OK;
+}
+
+// ------------------------------------------------------------------- gates
+qsv_status qsv_apply1q(qsv_state st, int q, const double* u) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+    HIP_OR_FAIL(ctx, launch_apply1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), u), "apply1q");
+    return QSV_OK;
+}
+
+qsv_status qsv_applyC1q(qsv_state st, int qc, int qt, int ctrl_state, const double* u) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+    if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "controlled gate needs n >= 2");
+    if (qc < 0 || qc >= st->n || qt < 0 || qt >= st->n)
+        return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+    if (qc == qt) return fail(ctx, QSV_ERR_QUBIT, "control equals target");
+    if (ctrl_state != 0 && ctrl_state != 1)
+        return fail(ctx, QSV_ERR_ARG, "control state must be 0 or 1");
+    HIP_OR_FAIL(ctx,
+                launch_applyc1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qc),
+                                pos_of(st->n, qt), ctrl_state, u),
+                "applyC1q");
+    return QSV_OK;
+}
+
+qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+    if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "2-qubit gate needs n >= 2");
+    if (qa < 0 || qa >= st->n || qb < 0 || qb >= st->n)
+        return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+    if (qa == qb) return fail(ctx, QSV_ERR_QUBIT, "repeated qubit");
+    HIP_OR_FAIL(ctx,
+                launch_apply2q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qa),
+                               pos_of(st->n, qb), u),
+                "apply2q");
+    return QSV_OK;
+}
+
+qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
+                             int64_t nparams, int flags) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
+    if (nparams < 0) return fail(ctx, QSV_ERR_ARG, "negative parameter count");
+    if (flags & ~QSV_FLAG_NO_FUSE) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+    std::vector<PGate> pg;
+    if (qsv_status s = lower(ctx, st->n, g, ng, params, nparams, pg)) return s;
+    if (pg.empty()) return QSV_OK;
+    if (flags & QSV_FLAG_NO_FUSE) {
+        for (const PGate& x : pg)
+            HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
+        return QSV_OK;
+    }
+    const TileConfig& cfg = st->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    std::vector<Pass> passes = plan_passes(st->n, pg, cfg);
+    HIP_OR_FAIL(ctx, run_passes(ctx, st->ptr, st->n, st->dtype, pg, passes), "tile passes");
+    return QSV_OK;
+}
+
+// -------------------------------------------------------------- reductions
+qsv_status qsv_norm2(qsv_state st, double* out) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
+    const uint64_t zero = 0;
+    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, st->n, st->dtype, 1, &zero, out), "norm2");
+    return QSV_OK;
+}
+
+qsv_status qsv_expect_z(qsv_state st, int nterms, const uint64_t* qmasks, const double* w,
+                        double* out_terms, double* out_sum) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (nterms < 1 || nterms > 4096 || !qmasks)
+        return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
+    const int n = st->n;
+    std::vector<uint64_t> pm(size_t(nterms), 0);
+    for (int t = 0; t < nterms; ++t) {
+        if (n < 64 && (qmasks[t] >> n))
+            return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
+        for (int q = 0; q < n; ++q)
+            if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
+    }
+    std::vector<double> terms(size_t(nterms), 0.0);
+    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, n, st->dtype, nterms, pm.data(), terms.data()),
+                "expect_z");
+    double sum = 0.0;
+    for (int t = 0; t < nterms; ++t) sum += (w ? w[t] : 1.0) * terms[t];
+    if (out_terms) std::memcpy(out_terms, terms.data(), sizeof(double) * nterms);
+    if (out_sum) *out_sum = sum;
+    return QSV_OK;
+}
+
+qsv_status qsv_inner(qsv_state a, qsv_state b, double* out) {
+    if (qsv_status s = check_state(a)) return s;
+    if (!b) return QSV_ERR_ARG;
+    qsv_ctx ctx = a->ctx;
+    if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
+    if (a->n != b->n) return fail(ctx, QSV_ERR_SIZE, "states have different qubit counts");
+    if (b->ctx->device != ctx->device) return fail(ctx, QSV_ERR_ARG, "states on different devices");
+    if (b->ctx != ctx) HIP_OR_FAIL(ctx, hipStreamSynchronize(b->ctx->stream), "sync b");
+    HIP_OR_FAIL(ctx, reduce_inner(ctx, a->ptr, a->dtype, b->ptr, b->dtype, a->n, out), "inner");
+    return QSV_OK;
+}
+
+qsv_status qsv_prob1(qsv_state st, int q, double* p1) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!p1) return fail(ctx, QSV_ERR_ARG, "null output");
+    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+    double r[2];
+    HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), r), "prob1");
+    *p1 = r[1];
+    return QSV_OK;
+}
+
+qsv_status qsv_measure1(qsv_state st, int q, double r, int* outcome) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    if (!outcome) return fail(ctx, QSV_ERR_ARG, "null output");
+    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+    if (!(r >= 0.0 && r < 1.0)) return fail(ctx, QSV_ERR_ARG, "r must lie in [0, 1)");
+    double p[2];
+    const int pos = pos_of(st->n, q);
+    HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos, p), "measure1");
+    int k = (r < p[0]) ? 0 : 1;
+    if (p[k] <= 0.0) k = 1 - k;   // r beyond a sub-unit total norm: take the other outcome
+    if (p[k] <= 0.0) return fail(ctx, QSV_ERR_ARG, "state has zero norm");
+    HIP_OR_FAIL(ctx, launch_collapse(ctx, st->ptr, st->n, st->dtype, pos, k, 1.0 / std::sqrt(p[k])),
+                "collapse");
+    *outcome = k;
+    return QSV_OK;
+}
+
+qsv_status qsv_copy_to_host(qsv_state st, void* host, size_t nbytes) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
+    if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
+    if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(host, st->ptr, need, hipMemcpyDeviceToHost, ctx->stream),
+                "hipMemcpyAsync D2H");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return QSV_OK;
+}
+
+qsv_status qsv_copy_from_host(qsv_state st, const void* host, size_t nbytes) {
+    if (qsv_status s = check_state(st)) return s;
+    qsv_ctx ctx = st->ctx;
+    const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
+    if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
+    if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(st->ptr, host, need, hipMemcpyHostToDevice, ctx->stream),
+                "hipMemcpyAsync H2D");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return QSV_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t ng,
+                       const double* params, int64_t nparams, int nterms, const uint64_t* qmasks,
+                       const double* w, double* expval, double* grad, int flags) {
+    if (qsv_status s = check_state(psi)) return s;
+    qsv_ctx ctx = psi->ctx;
+    if (!lam || lam->ctx != ctx) return fail(ctx, QSV_ERR_ARG, "co-state must share the context");
+    if (lam->n != psi->n) return fail(ctx, QSV_ERR_SIZE, "co-state has a different qubit count");
+    if (lam->dtype != psi->dtype) return fail(ctx, QSV_ERR_DTYPE, "co-state has a different dtype");
+    if (lam->ptr == psi->ptr) return fail(ctx, QSV_ERR_ARG, "co-state aliases the state");
+    if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
+    if (nparams < 0 || (nparams > 0 && (!params || !grad)))
+        return fail(ctx, QSV_ERR_ARG, "bad parameter arrays");
+    if (nterms < 1 || nterms > 4096 || !qmasks)
+        return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
+    if (flags & ~(QSV_FLAG_FORWARD | QSV_FLAG_NO_FUSE)) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+    const int n = psi->n;
+    std::vector<PGate> fwd;
+    if (qsv_status s = lower(ctx, n, g, ng, params, nparams, fwd)) return s;
+    std::vector<int> rot_param(size_t(ng), -1), rot_axis(size_t(ng), -1);
+    for (int64_t i = 0; i < ng; ++i)
+        if (g[i].kind == QSV_GROT) {
+            rot_param[size_t(i)] = g[i].param;
+            rot_axis[size_t(i)] = g[i].axis;
+        }
+    std::vector<uint64_t> pm(size_t(nterms), 0);
+    for (int t = 0; t < nterms; ++t) {
+        if (n < 64 && (qmasks[t] >> n))
+            return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
+        for (int q = 0; q < n; ++q)
+            if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
+    }
+    if (flags & QSV_FLAG_FORWARD) {
+        HIP_OR_FAIL(ctx, launch_init_basis(ctx, psi->ptr, n, psi->dtype, 0), "init");
+        if (!fwd.empty()) {
+            if (flags & QSV_FLAG_NO_FUSE) {
+                for (const PGate& x : fwd)
+                    HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
+            } else {
+                const TileConfig& cfg = psi->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+                HIP_OR_FAIL(ctx, run_passes(ctx, psi->ptr, n, psi->dtype, fwd,
+                                            plan_passes(n, fwd, cfg)),
+                            "forward passes");
+            }
+        }
+    }
+    std::vector<double> terms(size_t(nterms), 0.0);
+    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, psi->ptr, n, psi->dtype, nterms, pm.data(), terms.data()),
+                "expectation");
+    double f = 0.0;
+    for (int t = 0; t < nterms; ++t) f += (w ? w[t] : 1.0) * terms[size_t(t)];
+    std::vector<double> wv(size_t(nterms), 1.0);
+    if (w) std::memcpy(wv.data(), w, sizeof(double) * nterms);
+    std::vector<double> by_gate(size_t(ng), 0.0);
+    HIP_OR_FAIL(ctx,
+                run_adjoint(ctx, psi->ptr, lam->ptr, n, psi->dtype, fwd, rot_param, rot_axis,
+                            nterms, pm.data(), wv.data(), by_gate.data()),
+                "adjoint sweep");
+    for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
+    for (int64_t i = 0; i < ng; ++i)
+        if (rot_param[size_t(i)] >= 0) grad[rot_param[size_t(i)]] += by_gate[size_t(i)];
+    if (expval) *expval = f;
+    return QSV_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits) {
+    if (!ctx) return QSV_ERR_ARG;
+    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+    TileConfig& cfg = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    const int kmax = tile_bits_max(dtype);
+    const int tb = tile_bits ? tile_bits : kmax;
+    const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
+    if (tb < 4 || tb > kmax)
+        return fail(ctx, QSV_ERR_ARG, "tile_bits must be in [4, " + std::to_string(kmax) + "]");
+    if (lb < 0 || lb > tb - 2) return fail(ctx, QSV_ERR_ARG, "low_bits must be in [0, tile_bits-2]");
+    cfg.tile_bits = tb;
+    cfg.low_bits = lb;
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int tile_bits,
+                            int low_bits, int64_t* npasses, int32_t* pass_of_gate,
+                            int32_t* exec_order, uint64_t* pass_qubits) {
+    if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
+    if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
+    if (ng < 0 || (ng > 0 && (!g || !pass_of_gate || !exec_order || !pass_qubits)) || !npasses)
+        return QSV_ERR_ARG;
+    const int kmax = tile_bits_max(dtype);
+    const int tb = tile_bits ? tile_bits : kmax;
+    const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
+    if (tb < 4 || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
+    // positions only: rotations get a placeholder angle
+    std::vector<double> zeros(size_t(ng) + 1, 0.0);
+    std::vector<qsv_gate> gg(g, g + ng);
+    for (auto& x : gg)
+        if (x.kind == QSV_GROT) x.param = 0;
+    std::vector<PGate> pg;
+    if (qsv_status s = lower(nullptr, n, gg.data(), ng, zeros.data(), 1, pg)) return s;
+    std::vector<Pass> passes = plan_passes(n, pg, TileConfig{tb, lb});
+    int64_t k = 0;
+    for (size_t p = 0; p < passes.size(); ++p) {
+        uint64_t qm = 0;
+        for (int b = 0; b < passes[p].k; ++b) qm |= uint64_t(1) << pos_of(n, passes[p].pos[b]);
+        pass_qubits[p] = qm;
+        for (int gi : passes[p].gates) {
+            pass_of_gate[gi] = int32_t(p);
+            exec_order[k++] = gi;
+        }
+    }
+    *npasses = int64_t(passes.size());
+    return QSV_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+qsv_status qsv_profile_begin(qsv_ctx ctx) {
+    if (!ctx) return QSV_ERR_ARG;
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->prof.clear();
+    ctx->event_next = 0;
+    ctx->profiling = true;
+    return QSV_OK;
+}
+
+qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count) {
+    if (!ctx) return QSV_ERR_ARG;
+    ctx->profiling = false;
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    std::map<std::string, qsv_kstat> agg;
+    for (const ProfRec& r : ctx->prof) {
+        float ms = 0.f;
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, r.start, r.stop), "hipEventElapsedTime");
+        qsv_kstat& k = agg[r.name];
+        k.launches += 1;
+        k.ms += ms;
+        k.bytes += r.bytes;
+    }
+    int i = 0;
+    for (auto& kv : agg) {
+        if (out && i < max) {
+            qsv_kstat k = kv.second;
+            std::memset(k.name, 0, sizeof(k.name));
+            std::strncpy(k.name, kv.first.c_str(), sizeof(k.name) - 1);
+            out[i] = k;
+        }
+        ++i;
+    }
+    if (count) *count = i;
+    ctx->prof.clear();
+    ctx->event_next = 0;
+    return QSV_OK;
+}
+
+}  // extern "C"

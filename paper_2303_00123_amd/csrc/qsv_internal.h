@@ -1,0 +1,160 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qsv.h"
+
+namespace qsv {
+
+constexpr int kMaxQubits = 36;
+
+inline size_t amp_bytes(int dtype) { return dtype == QSV_C128 ? 16 : 8; }
+
+// ---------------------------------------------------------------- plans
+// A gate in index-bit coordinates: position p = n-1-q of qubit q.
+struct PGate {
+    int kind;       // QSV_G1Q, QSV_GC1Q, QSV_G2Q (rotations are lowered to G1Q)
+    int p0, p1;     // G1Q: p0 target; GC1Q: p0 control, p1 target; G2Q: p0 = pos(qa), p1 = pos(qb)
+    int cs;
+    double m[32];
+};
+
+// One fused pass over the state.
+struct Pass {
+    bool single;                 // true: one gate, unfused kernel
+    int k;                       // tile bits (tile = 2^k amplitudes)
+    int pos[24];                 // ascending global bit positions of the tile's local bits
+    std::vector<int> gates;      // indices into the lowered gate list, in execution order
+};
+
+struct TileConfig {
+    int tile_bits;   // log2 amplitudes per tile
+    int low_bits;    // contiguous low bits kept in every tile
+};
+
+// Group gates into passes (greedy, dependency-respecting).
+std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg);
+
+// Device-side gate record of a tile pass (local bit coordinates).
+template <typename R>
+struct TGate {
+    int32_t kind;
+    int32_t l0, l1;
+    int32_t cs;
+    R m[32];
+};
+
+// Pass header in device memory.
+struct TPassHdr {
+    int32_t k;
+    int32_t ngates;
+    int32_t pos[24];
+};
+
+// ------------------------------------------------------------- profiling
+struct ProfRec {
+    const char* name;
+    double bytes;
+    hipEvent_t start, stop;
+};
+
+}  // namespace qsv
+
+struct qsv_ctx_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cus = 256;
+    std::string last_error;
+
+    // reduction scratch: stage-1 partials and stage-2 results (fixed size)
+    double* d_red = nullptr;
+    double* h_red = nullptr;     // pinned, receives stage-2 results
+    // plan upload: pinned staging + device copy (grown on demand)
+    void* d_plan = nullptr;
+    size_t d_plan_bytes = 0;
+    void* h_plan = nullptr;
+    size_t h_plan_bytes = 0;
+    hipEvent_t plan_copied = nullptr;   // last H2D plan copy done -> h_plan reusable
+    // auxiliary device buffer (grown on demand): adjoint per-gate gradients
+    double* d_aux = nullptr;
+    size_t d_aux_doubles = 0;
+
+    qsv::TileConfig tile_c128{12, 3};
+    qsv::TileConfig tile_c64{13, 4};
+
+    // profiling
+    bool profiling = false;
+    std::vector<qsv::ProfRec> prof;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+
+    // batch scratch
+    void* d_batch = nullptr;
+    size_t batch_bytes = 0;
+    void* batch_graph_exec = nullptr;   // hipGraphExec_t
+    uint64_t batch_graph_key = 0;
+};
+
+struct qsv_state_s {
+    qsv_ctx ctx = nullptr;
+    void* ptr = nullptr;
+    int n = 0;
+    int dtype = QSV_C128;
+    bool owns = false;
+    size_t nbytes = 0;
+};
+
+namespace qsv {
+
+constexpr size_t kRedDoubles = 1 << 16;   // partials: up to 2048 blocks x 16 terms, + results
+
+// Plan upload (capi.cpp): returns a pinned host buffer of at least `bytes`
+// that is safe to overwrite, and after filling it, copies it to device memory.
+hipError_t plan_staging(qsv_ctx ctx, size_t bytes, void** host);
+hipError_t plan_upload(qsv_ctx ctx, size_t bytes, void** dev);
+hipError_t ensure_aux(qsv_ctx ctx, size_t doubles);
+
+// profiling helpers: bracket a launch
+void prof_before(qsv_ctx ctx, const char* name, double bytes);
+void prof_after(qsv_ctx ctx);
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on ctx->stream and return the launch status.
+hipError_t launch_init_basis(qsv_ctx ctx, void* s, int n, int dtype, uint64_t b);
+hipError_t launch_apply1q(qsv_ctx ctx, void* s, int n, int dtype, int p, const double* u);
+hipError_t launch_applyc1q(qsv_ctx ctx, void* s, int n, int dtype, int pc, int pt, int cs,
+                           const double* u);
+hipError_t launch_apply2q(qsv_ctx ctx, void* s, int n, int dtype, int pa, int pb, const double* u);
+hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g);
+
+// Largest tile (log2 amplitudes) the tile kernel supports for a dtype.
+int tile_bits_max(int dtype);
+
+// Tile passes: uploads the plan for all passes, then launches them in order.
+hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
+                      const std::vector<Pass>& passes);
+
+// Reductions.  Stage-1 partials go to ctx scratch; results land in host memory.
+// Z-string sums: out[t] = sum_x |s_x|^2 (-1)^{popcount(x & pmask[t])}, t < nt.
+hipError_t reduce_zstrings(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
+                           const uint64_t* pmasks, double* out);
+// out[0] = sum over x with bit p clear, out[1] = with bit p set, of |s_x|^2.
+hipError_t reduce_bit_split(qsv_ctx ctx, const void* s, int n, int dtype, int p, double* out);
+// <a|b>
+hipError_t reduce_inner(qsv_ctx ctx, const void* a, int dta, const void* b, int dtb, int n,
+                        double* out);
+// keep amplitudes whose bit p equals `keep`, scaled by `scale`; zero the rest.
+hipError_t launch_collapse(qsv_ctx ctx, void* s, int n, int dtype, int p, int keep, double scale);
+
+// Adjoint sweep (qsv_adjoint.hip).
+hipError_t run_adjoint(qsv_ctx ctx, void* psi, void* lam, int n, int dtype,
+                       const std::vector<PGate>& fwd, const std::vector<int>& rot_param,
+                       const std::vector<int>& rot_axis, int nterms, const uint64_t* pmasks,
+                       const double* w, double* grad_by_gate);
+
+}  // namespace qsv

@@ -1,0 +1,256 @@
+// Reductions over the state: Z-string expectations, norm, single-qubit
+// probabilities, inner products, and measurement collapse.  Accumulation is
+// FP64 for both state precisions, in a fixed two-stage tree (per-block
+// partials, then one block), so results are bit-reproducible for a given n.
+#include "qsv_common.h"
+#include "qsv_internal.h"
+
+namespace qsv {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTermsPerPass = 16;
+constexpr int kMaxBlocks = 2048;
+
+struct ZMasks {
+    uint64_t m[kTermsPerPass];
+    int nt;
+};
+
+// Number of stage-1 blocks for a 2^n reduction: a power of two, fixed by n.
+inline unsigned red_blocks(uint64_t N) {
+    uint64_t g = N / 4096;
+    if (g < 1) g = 1;
+    if (g > kMaxBlocks) g = kMaxBlocks;
+    return unsigned(g);
+}
+
+// Fixed-order tree over the block's threads; red holds NT x kThreads values.
+template <int NT>
+__device__ void block_tree(double (*red)[kThreads], double* out) {
+    for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+        __syncthreads();
+        if (int(threadIdx.x) < stride) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + stride];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NT) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <typename R>
+__device__ __forceinline__ double prob(const typename V2T<R>::type& v) {
+    const double x = double(v.x), y = double(v.y);
+    return x * x + y * y;
+}
+
+// out[t] over this block's contiguous chunk: sum |s_x|^2 (-1)^{popc(x & m_t)}
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_zstr(const typename V2T<R>::type* __restrict__ s,
+                                                   uint64_t N, uint64_t chunk, ZMasks zm,
+                                                   double* __restrict__ partials) {
+    __shared__ double red[kTermsPerPass][kThreads];
+    double acc[kTermsPerPass];
+#pragma unroll
+    for (int t = 0; t < kTermsPerPass; ++t) acc[t] = 0.0;
+    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
+    const uint64_t hi = lo + chunk < N ? lo + chunk : N;
+    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double p = prob<R>(s[x]);
+#pragma unroll
+        for (int t = 0; t < kTermsPerPass; ++t)
+            if (t < zm.nt) acc[t] += (__popcll(x & zm.m[t]) & 1) ? -p : p;
+    }
+#pragma unroll
+    for (int t = 0; t < kTermsPerPass; ++t) red[t][threadIdx.x] = acc[t];
+    block_tree<kTermsPerPass>(red, partials + size_t(blockIdx.x) * kTermsPerPass);
+}
+
+// out[0] = sum over bit p clear, out[1] = bit p set
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_split(const typename V2T<R>::type* __restrict__ s,
+                                                    uint64_t N, uint64_t chunk, int p,
+                                                    double* __restrict__ partials) {
+    __shared__ double red[2][kThreads];
+    double a0 = 0.0, a1 = 0.0;
+    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
+    const uint64_t hi = lo + chunk < N ? lo + chunk : N;
+    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double q = prob<R>(s[x]);
+        if ((x >> p) & 1) a1 += q;
+        else a0 += q;
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    block_tree<2>(red, partials + size_t(blockIdx.x) * 2);
+}
+
+// <a|b> = sum conj(a_x) b_x
+template <typename Ra, typename Rb>
+__global__ __launch_bounds__(kThreads) void k_inner(const typename V2T<Ra>::type* __restrict__ a,
+                                                    const typename V2T<Rb>::type* __restrict__ b,
+                                                    uint64_t N, uint64_t chunk,
+                                                    double* __restrict__ partials) {
+    __shared__ double red[2][kThreads];
+    double re = 0.0, im = 0.0;
+    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
+    const uint64_t hi = lo + chunk < N ? lo + chunk : N;
+    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double ar = a[x].x, ai = a[x].y, br = b[x].x, bi = b[x].y;
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+    red[0][threadIdx.x] = re;
+    red[1][threadIdx.x] = im;
+    block_tree<2>(red, partials + size_t(blockIdx.x) * 2);
+}
+
+// Stage 2: out[t] = sum over blocks g of partials[g*nt_stride + t], fixed order.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_final(const double* __restrict__ partials,
+                                                    int nblocks, int stride,
+                                                    double* __restrict__ out) {
+    __shared__ double red[NT][kThreads];
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+    for (int g = threadIdx.x; g < nblocks; g += kThreads) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] += partials[size_t(g) * stride + t];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) red[t][threadIdx.x] = acc[t];
+    block_tree<NT>(red, out);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_collapse(typename V2T<R>::type* __restrict__ s,
+                                                       uint64_t N, int p, int keep, R scale) {
+    using V = typename V2T<R>::type;
+    const uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (x >= N) return;
+    V v = s[x];
+    if (int((x >> p) & 1) == keep) {
+        v.x *= scale;
+        v.y *= scale;
+    } else {
+        v.x = R(0);
+        v.y = R(0);
+    }
+    s[x] = v;
+}
+
+// Copy nt stage-2 results to the pinned host buffer and wait.
+hipError_t fetch(qsv_ctx ctx, const double* dev, int nt, double* out) {
+    hipError_t e = hipMemcpyAsync(ctx->h_red, dev, sizeof(double) * nt, hipMemcpyDeviceToHost,
+                                  ctx->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    for (int t = 0; t < nt; ++t) out[t] = ctx->h_red[t];
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t zstrings_t(qsv_ctx ctx, const void* s, int n, int nt, const uint64_t* pmasks,
+                      double* out) {
+    using V = typename V2T<R>::type;
+    const uint64_t N = uint64_t(1) << n;
+    const unsigned G = red_blocks(N);
+    const uint64_t chunk = (N + G - 1) / G;
+    double* partials = ctx->d_red;
+    double* res = ctx->d_red + kMaxBlocks * kTermsPerPass;
+    for (int t0 = 0; t0 < nt; t0 += kTermsPerPass) {
+        ZMasks zm{};
+        zm.nt = nt - t0 < kTermsPerPass ? nt - t0 : kTermsPerPass;
+        for (int t = 0; t < zm.nt; ++t) zm.m[t] = pmasks[t0 + t];
+        prof_before(ctx, sizeof(R) == 8 ? "reduce_zstr_c128" : "reduce_zstr_c64",
+                    double(N) * sizeof(V));
+        hipLaunchKernelGGL(k_zstr<R>, dim3(G), dim3(kThreads), 0, ctx->stream,
+                           static_cast<const V*>(s), N, chunk, zm, partials);
+        prof_after(ctx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_final<kTermsPerPass>, dim3(1), dim3(kThreads), 0, ctx->stream,
+                           partials, int(G), kTermsPerPass, res);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = fetch(ctx, res, zm.nt, out + t0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t split_t(qsv_ctx ctx, const void* s, int n, int p, double* out) {
+    using V = typename V2T<R>::type;
+    const uint64_t N = uint64_t(1) << n;
+    const unsigned G = red_blocks(N);
+    const uint64_t chunk = (N + G - 1) / G;
+    double* partials = ctx->d_red;
+    double* res = ctx->d_red + kMaxBlocks * kTermsPerPass;
+    hipLaunchKernelGGL(k_split<R>, dim3(G), dim3(kThreads), 0, ctx->stream,
+                       static_cast<const V*>(s), N, chunk, p, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_final<2>, dim3(1), dim3(kThreads), 0, ctx->stream, partials, int(G), 2,
+                       res);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return fetch(ctx, res, 2, out);
+}
+
+template <typename Ra, typename Rb>
+hipError_t inner_t(qsv_ctx ctx, const void* a, const void* b, int n, double* out) {
+    using Va = typename V2T<Ra>::type;
+    using Vb = typename V2T<Rb>::type;
+    const uint64_t N = uint64_t(1) << n;
+    const unsigned G = red_blocks(N);
+    const uint64_t chunk = (N + G - 1) / G;
+    double* partials = ctx->d_red;
+    double* res = ctx->d_red + kMaxBlocks * kTermsPerPass;
+    hipLaunchKernelGGL((k_inner<Ra, Rb>), dim3(G), dim3(kThreads), 0, ctx->stream,
+                       static_cast<const Va*>(a), static_cast<const Vb*>(b), N, chunk, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_final<2>, dim3(1), dim3(kThreads), 0, ctx->stream, partials, int(G), 2,
+                       res);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return fetch(ctx, res, 2, out);
+}
+
+template <typename R>
+hipError_t collapse_t(qsv_ctx ctx, void* s, int n, int p, int keep, double scale) {
+    using V = typename V2T<R>::type;
+    const uint64_t N = uint64_t(1) << n;
+    const unsigned G = unsigned((N + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_collapse<R>, dim3(G), dim3(kThreads), 0, ctx->stream, static_cast<V*>(s),
+                       N, p, keep, R(scale));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t reduce_zstrings(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
+                           const uint64_t* pmasks, double* out) {
+    return dtype == QSV_C128 ? zstrings_t<double>(ctx, s, n, nt, pmasks, out)
+                             : zstrings_t<float>(ctx, s, n, nt, pmasks, out);
+}
+hipError_t reduce_bit_split(qsv_ctx ctx, const void* s, int n, int dtype, int p, double* out) {
+    return dtype == QSV_C128 ? split_t<double>(ctx, s, n, p, out) : split_t<float>(ctx, s, n, p, out);
+}
+hipError_t reduce_inner(qsv_ctx ctx, const void* a, int dta, const void* b, int dtb, int n,
+                        double* out) {
+    if (dta == QSV_C128 && dtb == QSV_C128) return inner_t<double, double>(ctx, a, b, n, out);
+    if (dta == QSV_C128) return inner_t<double, float>(ctx, a, b, n, out);
+    if (dtb == QSV_C128) return inner_t<float, double>(ctx, a, b, n, out);
+    return inner_t<float, float>(ctx, a, b, n, out);
+}
+hipError_t launch_collapse(qsv_ctx ctx, void* s, int n, int dtype, int p, int keep, double scale) {
+    return dtype == QSV_C128 ? collapse_t<double>(ctx, s, n, p, keep, scale)
+                             : collapse_t<float>(ctx, s, n, p, keep, scale);
+}
+
+}  // namespace qsv

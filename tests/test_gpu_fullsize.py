@@ -1,0 +1,98 @@
+"""Full-size checks at 30 qubits (16 GiB complex128 state), in the launch
+configuration the benchmark times (default fused tile passes).  No CPU
+oracle can hold every amplitude through a 1180-gate circuit here, so these
+use what holds at any size or what the oracle computes amplitude by
+amplitude:
+  * circuit then its inverse returns |0...0>;
+  * norm preservation;
+  * a product-state circuit (1-qubit gates only): sampled amplitudes equal
+    the oracle's product of per-qubit amplitudes;
+  * complex64 run of the same circuit agrees with complex128 (infidelity).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 30
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    free, _ = torch.cuda.mem_get_info()
+    if free < 30 * 2 ** 30:
+        pytest.skip("needs ~30 GiB of device memory")
+    import paper_2303_00123_amd as qq
+    return qq
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context()
+    yield c
+    c.close()
+
+
+def test_forward_then_inverse_is_identity(q, ctx):
+    c = W.layered_cnot_brick(N, 20, seed=3002)
+    st = q.State(ctx, N)
+    st.init_basis(0)
+    st.apply_circuit(c.gates)
+    n1 = st.norm2()
+    assert abs(n1 - 1.0) < 1e-11
+    terms, _ = st.expect_z(c.observable)
+    assert abs(terms[0]) <= 1.0
+    st.apply_circuit(W.inverse(c).gates)
+    a0 = complex(st.tensor[0].item())
+    assert abs(a0 - 1.0) < 1e-10
+    assert abs(st.norm2() - 1.0) < 1e-11
+    st.free()
+
+
+def test_product_circuit_sampled_amplitudes(q, ctx):
+    rng = np.random.default_rng(31)
+    layers = 3
+    gates = []
+    us = [[W.haar_unitary(2, rng) for _ in range(N)] for _ in range(layers)]
+    for layer in us:
+        for qb, u in enumerate(layer):
+            gates.append(W.g1(qb, u))
+    # per-qubit final 2-vectors, by the oracle's own 1-qubit gate applications
+    qstates = []
+    for qb in range(N):
+        v = O.basis(1)
+        for layer in us:
+            v = O.apply_1q(v, 0, layer[qb])
+        qstates.append(v)
+    qstates = np.array(qstates)
+    st = q.State(ctx, N)
+    st.init_basis(0)
+    st.apply_circuit(gates)
+    import torch
+    xs = np.concatenate([[0, 2 ** N - 1, 1, 2 ** (N - 1)], rng.integers(0, 2 ** N, size=60)])
+    got = st.tensor[torch.as_tensor(xs, device="cuda")].cpu().numpy()
+    ref = np.array([O.product_amplitude(qstates, int(x)) for x in xs])
+    assert np.max(np.abs(got - ref)) < 1e-12
+    assert abs(st.norm2() - 1.0) < 1e-12
+    st.free()
+
+
+def test_c64_matches_c128_full_size(q, ctx):
+    c = W.layered_cnot_brick(N, 5, seed=3005)
+    a = q.State(ctx, N, q.QSV_C128)
+    a.init_basis(0)
+    a.apply_circuit(c.gates)
+    b = q.State(ctx, N, q.QSV_C64)
+    b.init_basis(0)
+    b.apply_circuit(c.gates)
+    ov = b.inner(a)
+    assert 1.0 - abs(ov) ** 2 <= 1e-6
+    assert abs(b.norm2() - 1.0) <= 1e-5
+    b.free()
+    a.free()

@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/qsv.h declares, the gate record layout agrees with the
+header, and the fusion planner (host logic) produces a valid plan."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2303_00123_amd as q
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsv.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:qsv_status|const char\*)\s+(qsv_\w+)\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = q.lib()
+    declared = header_functions()
+    assert len(declared) >= 25
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(q.EXPORTS) == declared
+
+
+def test_status_strings():
+    L = q.lib()
+    assert L.qsv_status_str(0) == b"ok"
+    assert L.qsv_status_str(2) == b"invalid qubit index"
+    assert L.qsv_status_str(99) == b"unknown status"
+
+
+def test_gate_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "qsv.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(qsv_gate),'
+                   ' offsetof(qsv_gate, param), offsetof(qsv_gate, m), sizeof(qsv_kstat));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    size, off_param, off_m, kst = map(int, subprocess.check_output([str(exe)]).split())
+    assert size == q.qsv.GATE_DTYPE.itemsize == 280
+    assert off_param == q.qsv.GATE_DTYPE.fields["param"][1]
+    assert off_m == q.qsv.GATE_DTYPE.fields["m"][1]
+    assert kst == ctypes.sizeof(q.qsv.KStat)
+
+
+def test_header_compiles_as_c_and_cpp(tmp_path):
+    for lang, comp in (("c", "gcc"), ("c++", "g++")):
+        src = tmp_path / ("h." + ("c" if lang == "c" else "cpp"))
+        src.write_text('#include "qsv.h"\nint main(void){return QSV_OK;}\n')
+        subprocess.run([comp, "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(tmp_path / ("a_" + lang.replace("+", "p")))], check=True)
+
+
+def test_ctx_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    st = q.lib().qsv_ctx_create(None, ctypes.byref(h))
+    assert st != 0 and not h.value
+
+
+# ------------------------------------------------------------------ planner
+def _check_plan(c, tile_bits, low_bits, dtype=q.QSV_C128):
+    pog, order, pq = q.plan_circuit(c.n, c.gates, dtype, tile_bits, low_bits)
+    ng = len(c.gates)
+    assert sorted(order.tolist()) == list(range(ng))
+    # passes are executed in order; within a pass, circuit order is kept
+    assert np.all(np.diff(pog[order]) >= 0)
+    for p in range(len(pq)):
+        members = order[pog[order] == p]
+        assert np.all(np.diff(members) > 0)
+    kbits = min(tile_bits or 12, c.n)
+    lbits = min(low_bits or 3, kbits)
+    for p, mask in enumerate(pq):
+        mask = int(mask)
+        assert bin(mask).count("1") == kbits
+        for ql in range(c.n - lbits, c.n):            # lowest index bits = highest qubits
+            assert (mask >> ql) & 1
+    for i, g in enumerate(c.gates):
+        mask = int(pq[pog[i]])
+        for qq in g.qubits:
+            assert (mask >> qq) & 1, (i, g.qubits)
+    # a gate may overtake an earlier one only if they share no qubit
+    pos = np.empty(ng, dtype=np.int64)
+    pos[order] = np.arange(ng)
+    for i in range(ng):
+        for j in range(i + 1, ng):
+            if pos[j] < pos[i]:
+                assert not set(c.gates[i].qubits) & set(c.gates[j].qubits), (i, j)
+    return pog, order, pq
+
+
+@pytest.mark.parametrize("n,tb,lb", [(14, 0, 0), (16, 8, 2), (13, 12, 3), (9, 0, 0), (15, 6, 0)])
+def test_planner_valid_on_random_mix(n, tb, lb):
+    c = W.random_mix(n, 150, seed=n * 7 + tb)
+    _check_plan(c, tb, lb)
+
+
+def test_planner_reordered_circuit_is_equivalent():
+    """Executing the gates in the planned order gives the same state (the
+    oracle runs both orders)."""
+    c = W.random_mix(12, 200, seed=77)
+    _, order, _ = _check_plan(c, 8, 2)
+    re = W.Circuit(c.n, [c.gates[i] for i in order])
+    phi = W.random_state(c.n, 5)
+    assert np.max(np.abs(O.run(re, phi) - O.run(c, phi))) < 1e-13
+
+
+def test_planner_fuses_layered_circuit():
+    c = W.layered_cnot_brick(30, 20, seed=3002)
+    pog, order, pq = _check_plan(c, 0, 0)
+    # one pass per gate would be 1180 passes; fusion must do far better
+    assert len(pq) < len(c.gates) / 8
+
+
+def test_planner_small_state_single_pass():
+    c = W.config1()       # n = 10 <= tile bits: the whole circuit is one pass
+    pog, order, pq = q.plan_circuit(c.n, c.gates)
+    assert len(pq) == 1 and np.all(pog == 0)
+    assert list(order) == list(range(len(c.gates)))

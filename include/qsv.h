@@ -243,8 +243,9 @@ qsv_status qsv_profile_begin(qsv_ctx ctx);
 qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
 
 /* Tile shape of the context's later fused passes for one dtype.
- * tile_bits: log2 of the amplitudes per tile, in [4, 12] for QSV_C128 and
- * [4, 13] for QSV_C64 (0 = the maximum).  low_bits: number of lowest index
+ * tile_bits: log2 of the amplitudes per tile, in [10, 12] for QSV_C128 and
+ * [10, 13] for QSV_C64 (0 = the maximum).  States with fewer than 10 qubits
+ * run one kernel per gate.  low_bits: number of lowest index
  * bits every tile keeps, so each tile is made of contiguous runs of
  * 2^low_bits amplitudes; in [0, tile_bits - 2] (0 = 3 for QSV_C128, 4 for
  * QSV_C64, i.e. 128-byte runs). */
@@ -254,7 +255,8 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits);
  * n-qubit circuit (no device work; needs no GPU).  tile_bits / low_bits as in
  * qsv_set_tile (0 = defaults for dtype).  Outputs, each an array of at least
  * ng entries: pass_of_gate[i] = pass that applies gate i; exec_order = gate
- * indices in execution order; pass_qubits[p] = qubit mask (bit q = qubit q)
+ * indices in the order the kernels apply them (passes in sequence; inside a
+ * pass, its register stages in sequence); pass_qubits[p] = qubit mask (bit q = qubit q)
  * of pass p's tile.  *npasses receives the number of passes. */
 qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int tile_bits,
                             int low_bits, int64_t* npasses, int32_t* pass_of_gate,

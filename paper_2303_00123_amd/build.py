@@ -7,7 +7,9 @@ parallel, then linked into paper_2303_00123_amd/libqsv.so.  Run directly
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -29,9 +31,16 @@ SOURCES = [
 ]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
+# -simplifycfg-sink-common=false: the tile kernel's compile-time register
+#   index maps live in switch cases; sinking their common code would turn the
+#   constant indices into a runtime-selected one and push the per-thread
+#   amplitude array out of registers into scratch memory.
+# kernel-resource-usage remarks are parsed to reject any kernel that spills.
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-simplifycfg-sink-common=false",
+    "-Rpass-analysis=kernel-resource-usage",
 ]
 
 
@@ -48,7 +57,27 @@ def _compile(src: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    usage = parse_resource_usage(r.stderr)
+    spills = {k: v for k, v in usage.items() if v.get("ScratchSize [bytes/lane]", 0) > 0}
+    if spills:
+        raise RuntimeError(f"{src}: kernels use scratch memory: {sorted(spills)}")
+    with open(obj + ".usage.json", "w") as f:
+        json.dump(usage, f, indent=1, sort_keys=True)
     return obj
+
+
+def parse_resource_usage(text: str) -> dict:
+    """Kernel name -> {field: int} from -Rpass-analysis=kernel-resource-usage."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([^:]+): (\d+) \[-Rpass-analysis", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = int(m.group(2))
+    return out
 
 
 def build(verbose: bool = False) -> str:

@@ -604,8 +604,9 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits) {
     const int kmax = tile_bits_max(dtype);
     const int tb = tile_bits ? tile_bits : kmax;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    if (tb < 4 || tb > kmax)
-        return fail(ctx, QSV_ERR_ARG, "tile_bits must be in [4, " + std::to_string(kmax) + "]");
+    if (tb < kMinTileBits || tb > kmax)
+        return fail(ctx, QSV_ERR_ARG, "tile_bits must be in [" + std::to_string(kMinTileBits) + ", " +
+                                          std::to_string(kmax) + "]");
     if (lb < 0 || lb > tb - 2) return fail(ctx, QSV_ERR_ARG, "low_bits must be in [0, tile_bits-2]");
     cfg.tile_bits = tb;
     cfg.low_bits = lb;
@@ -622,7 +623,7 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
     const int kmax = tile_bits_max(dtype);
     const int tb = tile_bits ? tile_bits : kmax;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    if (tb < 4 || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
+    if (tb < kMinTileBits || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
     // positions only: rotations get a placeholder angle
     std::vector<double> zeros(size_t(ng) + 1, 0.0);
     std::vector<qsv_gate> gg(g, g + ng);
@@ -636,9 +637,12 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
         uint64_t qm = 0;
         for (int b = 0; b < passes[p].k; ++b) qm |= uint64_t(1) << pos_of(n, passes[p].pos[b]);
         pass_qubits[p] = qm;
-        for (int gi : passes[p].gates) {
-            pass_of_gate[gi] = int32_t(p);
-            exec_order[k++] = gi;
+        for (int gi : passes[p].gates) pass_of_gate[gi] = int32_t(p);
+        if (passes[p].single || passes[p].stages.empty()) {
+            for (int gi : passes[p].gates) exec_order[k++] = gi;
+        } else {
+            for (const Stage& st : passes[p].stages)
+                for (int gi : st.gates) exec_order[k++] = gi;
         }
     }
     *npasses = int64_t(passes.size());

@@ -24,12 +24,21 @@ struct PGate {
     double m[32];
 };
 
+// A stage of a tile pass: the gates applied while each thread holds the
+// amplitudes spanning `rbits` (local tile bits) in registers.
+struct Stage {
+    int nr = 0;                  // register bits used by this pass's kernel (= tile bits - 8)
+    int rbits[8] = {0};          // register bit j <-> local tile bit rbits[j]
+    std::vector<int> gates;      // indices into the lowered gate list, in execution order
+};
+
 // One fused pass over the state.
 struct Pass {
-    bool single;                 // true: one gate, unfused kernel
-    int k;                       // tile bits (tile = 2^k amplitudes)
-    int pos[24];                 // ascending global bit positions of the tile's local bits
+    bool single = false;         // true: one gate, unfused kernel
+    int k = 0;                   // tile bits (tile = 2^k amplitudes)
+    int pos[24] = {0};           // ascending global bit positions of the tile's local bits
     std::vector<int> gates;      // indices into the lowered gate list, in execution order
+    std::vector<Stage> stages;   // stage 0 and the last stage use the canonical mapping
 };
 
 struct TileConfig {
@@ -37,22 +46,46 @@ struct TileConfig {
     int low_bits;    // contiguous low bits kept in every tile
 };
 
-// Group gates into passes (greedy, dependency-respecting).
+constexpr int kTileThreads = 256;   // threads per tile workgroup (8 thread bits)
+constexpr int kMinTileBits = 10;    // at least 2 register bits per thread
+
+// Group gates into passes (greedy, dependency-respecting), then split each
+// tile pass into register stages.
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg);
 
-// Device-side gate record of a tile pass (local bit coordinates).
+// Device-side gate kinds inside a tile pass.
+enum {
+    DK_1Q = 0,    // generic 2x2 on register bit r0
+    DK_1D = 1,    // diagonal 2x2: m[0..1] = d0, m[2..3] = d1
+    DK_C1Q = 2,   // generic 2x2 on r1 where register bit r0 == cs
+    DK_CX = 3,    // swap on r1 where r0 == cs (controlled X)
+    DK_CD = 4,    // diagonal (d0, d1) on r1 where r0 == cs
+    DK_2Q = 5     // generic 4x4 on (r0, r1), local index 2*x_r0 + x_r1
+};
+
+// Device-side gate record of a tile pass (register bit coordinates).
 template <typename R>
 struct TGate {
     int32_t kind;
-    int32_t l0, l1;
+    int32_t r0, r1;
     int32_t cs;
     R m[32];
 };
 
-// Pass header in device memory.
+// Stage record in device memory.
+struct TStage {
+    int32_t gbeg, gend;     // gate range [gbeg, gend) of the pass's gate array
+    int32_t rbits[8];       // register bit j <-> local bit
+    int32_t tbits[8];       // thread-id bit j <-> local bit
+};
+
+// Pass header in device memory; followed by nstages TStage records and then
+// the pass's TGate records.
 struct TPassHdr {
     int32_t k;
+    int32_t nstages;
     int32_t ngates;
+    int32_t pad;
     int32_t pos[24];
 };
 

@@ -1,21 +1,30 @@
-// Fused tile pass: one workgroup loads a tile of 2^k amplitudes spanning the
-// pass's k index-bit positions into LDS, applies every gate of the pass to
-// it, and writes it back -- one HBM read and one HBM write for the whole
-// gate group.  Tile t of the pass covers the indices whose non-tile bits
-// spell t (zero-bit insertion at each tile position, ascending, generalising
-// the masks of Sec. 2.1-2.2 from one or two positions to k).  Because the
-// tile positions always include the lowest bits, each tile is a set of
-// contiguous runs of at least 2^low_bits amplitudes.
+// Fused tile pass.
 //
-// Inside the tile the gates use the same pair/quad index maps as the
-// unfused kernels (Algs. 1-3), on local bit positions.
+// One workgroup of 256 threads owns a tile of 2^K amplitudes spanning the
+// pass's K index-bit positions: tile t covers the indices whose non-tile
+// bits spell t (zero-bit insertion at each tile position, ascending -- the
+// masks of Sec. 2.1-2.2 generalised from one or two positions to K).  The
+// tile positions always include the lowest bits, so a tile is a set of
+// contiguous runs and the loads and stores stay coalesced.
+//
+// Each thread holds P = 2^(K-8) amplitudes in registers.  A gate whose bits
+// are all register bits is applied without leaving registers, with the
+// pair/quad index maps of Algs. 1-3 resolved at compile time (one code path
+// per register-bit choice).  Between stages the tile is re-mapped through
+// LDS, so different local bits become register bits.  HBM sees one read and
+// one write of the tile for the whole gate group.
+//
+// LDS holds the tile with an XOR swizzle on the 16-byte (c128) or 8-byte
+// (c64) slot index, so strided stage mappings spread over the banks.
+#include <type_traits>
+
 #include "qsv_common.h"
 #include "qsv_internal.h"
 
 namespace qsv {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kTileThreads;
 
 template <typename R>
 struct TileK;
@@ -24,159 +33,282 @@ struct TileK<double> { static constexpr int value = 12; };   // 4096 x 16 B = 64
 template <>
 struct TileK<float> { static constexpr int value = 13; };    // 8192 x 8 B = 64 KiB
 
-// Global offset of local element index e: deposit e's bits at pos[].
+template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t e);
+template <>
+__device__ __forceinline__ uint32_t swz<double>(uint32_t e) {
+    return e ^ (((e >> 4) ^ (e >> 8)) & 15u);
+}
+template <>
+__device__ __forceinline__ uint32_t swz<float>(uint32_t e) {
+    return e ^ (((e >> 5) ^ (e >> 10)) & 31u);
+}
+
+// Deposit the low `k` bits of e at the positions pos[0..k).
 __device__ __forceinline__ uint64_t deposit(uint32_t e, const int32_t* pos, int k) {
     uint64_t off = 0;
     for (int i = 0; i < k; ++i)
         if ((e >> i) & 1u) off |= uint64_t(1) << pos[i];
     return off;
 }
+__device__ __forceinline__ uint32_t deposit32(uint32_t e, const int32_t* pos, int k) {
+    uint32_t off = 0;
+    for (int i = 0; i < k; ++i)
+        if ((e >> i) & 1u) off |= 1u << pos[i];
+    return off;
+}
 
-template <typename R, int KMAX>
+template <int B>
+using IC = std::integral_constant<int, B>;
+
+// ---------------------------------------------------- register gate bodies
+template <int B, typename R, typename V, int P>
+__device__ __forceinline__ void rg_1q(V (&v)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!(i & (1 << B))) {
+            const V a = v[i], b = v[i | (1 << B)];
+            mv2(m, a, b, v[i], v[i | (1 << B)]);
+        }
+}
+
+template <typename R, typename V>
+__device__ __forceinline__ V cmul(const V& a, R dr, R di) {
+    V o;
+    o.x = a.x * dr - a.y * di;
+    o.y = a.x * di + a.y * dr;
+    return o;
+}
+
+template <int B, typename R, typename V, int P>
+__device__ __forceinline__ void rg_1d(V (&v)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        if (i & (1 << B)) v[i] = cmul(v[i], m[2], m[3]);
+        else v[i] = cmul(v[i], m[0], m[1]);
+    }
+}
+
+template <int C, int T, int CS, typename R, typename V, int P>
+__device__ __forceinline__ void rg_c1q(V (&v)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
+            const V a = v[i], b = v[i | (1 << T)];
+            mv2(m, a, b, v[i], v[i | (1 << T)]);
+        }
+}
+
+template <int C, int T, int CS, typename V, int P>
+__device__ __forceinline__ void rg_cx(V (&v)[P]) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
+            const V a = v[i];
+            v[i] = v[i | (1 << T)];
+            v[i | (1 << T)] = a;
+        }
+}
+
+template <int C, int T, int CS, typename R, typename V, int P>
+__device__ __forceinline__ void rg_cd(V (&v)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (((i >> C) & 1) == CS) {
+            if (i & (1 << T)) v[i] = cmul(v[i], m[2], m[3]);
+            else v[i] = cmul(v[i], m[0], m[1]);
+        }
+}
+
+template <int A, int B, typename R, typename V, int P>
+__device__ __forceinline__ void rg_2q(V (&v)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!(i & (1 << A)) && !(i & (1 << B))) {
+            V in[4], out[4];
+            in[0] = v[i];
+            in[1] = v[i | (1 << B)];
+            in[2] = v[i | (1 << A)];
+            in[3] = v[i | (1 << A) | (1 << B)];
+            mv4(m, in, out);
+            v[i] = out[0];
+            v[i | (1 << B)] = out[1];
+            v[i | (1 << A)] = out[2];
+            v[i | (1 << A) | (1 << B)] = out[3];
+        }
+}
+
+// ------------------------------------------------------ runtime dispatch
+template <int RB, typename F>
+__device__ __forceinline__ void on_bit(int b, F&& f) {
+    switch (b) {
+    case 0: f(IC<0>{}); break;
+    case 1: f(IC<1>{}); break;
+    case 2: if constexpr (RB > 2) f(IC<2>{}); break;
+    case 3: if constexpr (RB > 3) f(IC<3>{}); break;
+    case 4: if constexpr (RB > 4) f(IC<4>{}); break;
+    default: if constexpr (RB > 5) f(IC<5>{}); break;
+    }
+}
+
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_gate(V (&v)[P], const TGate<R>& g) {
+    const int kind = g.kind;
+    if (kind == DK_1Q) {
+        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1q<decltype(B)::value>(v, g.m); });
+    } else if (kind == DK_1D) {
+        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1d<decltype(B)::value>(v, g.m); });
+    } else if (kind == DK_2Q) {
+        on_bit<RB>(g.r0, [&](auto A) __attribute__((always_inline)) {
+            on_bit<RB>(g.r1, [&](auto B) __attribute__((always_inline)) {
+                if constexpr (decltype(A)::value != decltype(B)::value)
+                    rg_2q<decltype(A)::value, decltype(B)::value>(v, g.m);
+            });
+        });
+    } else {
+        const int cs = g.cs;
+        on_bit<RB>(g.r0, [&](auto C) __attribute__((always_inline)) {
+            on_bit<RB>(g.r1, [&](auto T) __attribute__((always_inline)) {
+                constexpr int c = decltype(C)::value, t = decltype(T)::value;
+                if constexpr (c != t) {
+                    if (kind == DK_CX) {
+                        if (cs) rg_cx<c, t, 1>(v);
+                        else rg_cx<c, t, 0>(v);
+                    } else if (kind == DK_CD) {
+                        if (cs) rg_cd<c, t, 1>(v, g.m);
+                        else rg_cd<c, t, 0>(v, g.m);
+                    } else {
+                        if (cs) rg_c1q<c, t, 1>(v, g.m);
+                        else rg_c1q<c, t, 0>(v, g.m);
+                    }
+                }
+            });
+        });
+    }
+}
+
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restrict__ gates, int gb,
+                                            int ge) {
+    for (int g = gb; g < ge; ++g) apply_gate<RB>(v, gates[g]);
+}
+
+// ------------------------------------------------------------ the kernel
+template <typename R, int K>
 __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __restrict__ s,
-                                                   const TPassHdr* __restrict__ hdr,
-                                                   const TGate<R>* __restrict__ gates) {
+                                                   const char* __restrict__ plan) {
     using V = typename V2T<R>::type;
-    constexpr int EMAX = 1 << KMAX;
-    constexpr int PER = EMAX / kThreads;   // elements per thread at k = KMAX
-    __shared__ V tile[EMAX];
+    constexpr int E = 1 << K;
+    constexpr int RB = K - 8;
+    constexpr int P = 1 << RB;
+    __shared__ V tile[E];
 
-    const int k = hdr->k;
-    const int ng = hdr->ngates;
-    const uint32_t E = 1u << k;
+    const TPassHdr* hdr = reinterpret_cast<const TPassHdr*>(plan);
+    const TStage* stg = reinterpret_cast<const TStage*>(plan + sizeof(TPassHdr));
+    const int nst = hdr->nstages;
+    const TGate<R>* gates = reinterpret_cast<const TGate<R>*>(plan + sizeof(TPassHdr) +
+                                                              size_t(nst) * sizeof(TStage));
     const uint32_t tid = threadIdx.x;
 
-    // base index of this tile: insert a zero at every tile position
     uint64_t base = blockIdx.x;
-    for (int i = 0; i < k; ++i) base = insert0(base, hdr->pos[i]);
-    const int klo = k < 8 ? k : 8;
-    const uint64_t dt = base | deposit(tid, hdr->pos, klo);
+#pragma unroll
+    for (int i = 0; i < K; ++i) base = insert0(base, hdr->pos[i]);
+    const uint64_t dt = base | deposit(tid, hdr->pos, 8);
 
-    // ---- load: element e = u*256 + tid
-    {
-        V buf[PER];
+    V v[P];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t e = uint32_t(u) * kThreads + tid;
-            if (e < E) {
-                const uint64_t dm = deposit(uint32_t(u), hdr->pos + 8, k - 8 > 0 ? k - 8 : 0);
-                buf[u] = s[dt | dm];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t e = uint32_t(u) * kThreads + tid;
-            if (e < E) tile[e] = buf[u];
-        }
-    }
-    __syncthreads();
+    for (int u = 0; u < P; ++u) v[u] = s[dt | deposit(uint32_t(u), hdr->pos + 8, RB)];
+    apply_range<RB>(v, gates, stg[0].gbeg, stg[0].gend);
 
-    // ---- gates
-    for (int g = 0; g < ng; ++g) {
-        const TGate<R>& G = gates[g];
-        const int kind = G.kind;
-        if (kind == QSV_G1Q) {
-            const int l = G.l0;
-            const uint32_t w = 1u << l;
-            constexpr int NP = EMAX / 2 / kThreads;
-            V a[NP], b[NP];
+    if (nst > 1) {
 #pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 2) {
-                    const uint32_t ia = insert0_32(j, l);
-                    a[u] = tile[ia];
-                    b[u] = tile[ia + w];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 2) {
-                    const uint32_t ia = insert0_32(j, l);
-                    V oa, ob;
-                    mv2(G.m, a[u], b[u], oa, ob);
-                    tile[ia] = oa;
-                    tile[ia + w] = ob;
-                }
-            }
-        } else if (kind == QSV_GC1Q) {
-            const int lc = G.l0, lt = G.l1;
-            const int llo = lc < lt ? lc : lt, lhi = lc < lt ? lt : lc;
-            const uint32_t wt = 1u << lt;
-            const uint32_t wc = G.cs ? (1u << lc) : 0u;
-            constexpr int NP = EMAX / 4 / kThreads > 0 ? EMAX / 4 / kThreads : 1;
-            V a[NP], b[NP];
-#pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 4) {
-                    const uint32_t ia = insert0_32(insert0_32(j, llo), lhi) | wc;
-                    a[u] = tile[ia];
-                    b[u] = tile[ia + wt];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 4) {
-                    const uint32_t ia = insert0_32(insert0_32(j, llo), lhi) | wc;
-                    V oa, ob;
-                    mv2(G.m, a[u], b[u], oa, ob);
-                    tile[ia] = oa;
-                    tile[ia + wt] = ob;
-                }
-            }
-        } else {
-            const int la = G.l0, lb = G.l1;
-            const int llo = la < lb ? la : lb, lhi = la < lb ? lb : la;
-            const uint32_t wa = 1u << la, wb = 1u << lb;
-            constexpr int NQ = EMAX / 4 / kThreads > 0 ? EMAX / 4 / kThreads : 1;
-            V v[NQ][4];
-#pragma unroll
-            for (int u = 0; u < NQ; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 4) {
-                    const uint32_t i0 = insert0_32(insert0_32(j, llo), lhi);
-                    v[u][0] = tile[i0];
-                    v[u][1] = tile[i0 + wb];
-                    v[u][2] = tile[i0 + wa];
-                    v[u][3] = tile[i0 + wa + wb];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NQ; ++u) {
-                const uint32_t j = uint32_t(u) * kThreads + tid;
-                if (j < E / 4) {
-                    const uint32_t i0 = insert0_32(insert0_32(j, llo), lhi);
-                    V o[4];
-                    mv4(G.m, v[u], o);
-                    tile[i0] = o[0];
-                    tile[i0 + wb] = o[1];
-                    tile[i0 + wa] = o[2];
-                    tile[i0 + wa + wb] = o[3];
-                }
-            }
-        }
+        for (int u = 0; u < P; ++u) tile[swz<R>(uint32_t(u) * kThreads + tid)] = v[u];
         __syncthreads();
-    }
-
-    // ---- store
-    {
-        V buf[PER];
+        for (int st = 1; st < nst - 1; ++st) {
+            const TStage& S = stg[st];
+            const uint32_t eb = deposit32(tid, S.tbits, 8);
+            uint32_t ea[P];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t e = uint32_t(u) * kThreads + tid;
-            if (e < E) buf[u] = tile[e];
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t e = uint32_t(u) * kThreads + tid;
-            if (e < E) {
-                const uint64_t dm = deposit(uint32_t(u), hdr->pos + 8, k - 8 > 0 ? k - 8 : 0);
-                s[dt | dm] = buf[u];
+            for (int u = 0; u < P; ++u) {
+                ea[u] = swz<R>(eb | deposit32(uint32_t(u), S.rbits, RB));
+                v[u] = tile[ea[u]];
             }
+            apply_range<RB>(v, gates, S.gbeg, S.gend);
+#pragma unroll
+            for (int u = 0; u < P; ++u) tile[ea[u]] = v[u];
+            __syncthreads();
         }
+#pragma unroll
+        for (int u = 0; u < P; ++u) v[u] = tile[swz<R>(uint32_t(u) * kThreads + tid)];
+        apply_range<RB>(v, gates, stg[nst - 1].gbeg, stg[nst - 1].gend);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) s[dt | deposit(uint32_t(u), hdr->pos + 8, RB)] = v[u];
+}
+
+// ------------------------------------------------------------ host side
+bool is_zero(double x) { return x == 0.0; }
+
+// Returns false if a gate bit is not a register bit of its stage (a planner bug).
+template <typename R>
+bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t) {
+    int reg[32];
+    for (int b = 0; b < 32; ++b) reg[b] = -1;
+    for (int j = 0; j < st.nr; ++j) reg[st.rbits[j]] = j;
+    for (int m = 0; m < 32; ++m) t.m[m] = R(0);
+    t.cs = g.cs;
+    t.r0 = reg[loc[g.p0]];
+    t.r1 = g.kind == QSV_G1Q ? 0 : reg[loc[g.p1]];
+    if (loc[g.p0] < 0 || t.r0 < 0 || t.r1 < 0 || (g.kind != QSV_G1Q && (loc[g.p1] < 0 || t.r0 == t.r1)))
+        return false;
+    const double* m = g.m;
+    if (g.kind == QSV_G1Q) {
+        if (is_zero(m[2]) && is_zero(m[3]) && is_zero(m[4]) && is_zero(m[5])) {
+            t.kind = DK_1D;
+            t.m[0] = R(m[0]); t.m[1] = R(m[1]); t.m[2] = R(m[6]); t.m[3] = R(m[7]);
+        } else {
+            t.kind = DK_1Q;
+            for (int i = 0; i < 8; ++i) t.m[i] = R(m[i]);
+        }
+    } else if (g.kind == QSV_GC1Q) {
+        const bool offzero = is_zero(m[2]) && is_zero(m[3]) && is_zero(m[4]) && is_zero(m[5]);
+        const bool is_x = is_zero(m[0]) && is_zero(m[1]) && m[2] == 1.0 && is_zero(m[3]) &&
+                          m[4] == 1.0 && is_zero(m[5]) && is_zero(m[6]) && is_zero(m[7]);
+        if (is_x) {
+            t.kind = DK_CX;
+        } else if (offzero) {
+            t.kind = DK_CD;
+            t.m[0] = R(m[0]); t.m[1] = R(m[1]); t.m[2] = R(m[6]); t.m[3] = R(m[7]);
+        } else {
+            t.kind = DK_C1Q;
+            for (int i = 0; i < 8; ++i) t.m[i] = R(m[i]);
+        }
+    } else {
+        t.kind = DK_2Q;
+        for (int i = 0; i < 32; ++i) t.m[i] = R(m[i]);
+    }
+    return true;
+}
+
+template <typename R, int K>
+hipError_t launch_tile(qsv_ctx ctx, void* s, int n, const char* dplan) {
+    using V = typename V2T<R>::type;
+    const unsigned tiles = unsigned(uint64_t(1) << (n - K));
+    hipLaunchKernelGGL((k_tile<R, K>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
+                       static_cast<V*>(s), dplan);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, const char* dplan) {
+    switch (k) {
+    case 10: return launch_tile<R, 10>(ctx, s, n, dplan);
+    case 11: return launch_tile<R, 11>(ctx, s, n, dplan);
+    case 12: return launch_tile<R, 12>(ctx, s, n, dplan);
+    case 13:
+        if constexpr (TileK<R>::value >= 13) return launch_tile<R, 13>(ctx, s, n, dplan);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -184,14 +316,16 @@ template <typename R>
 hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& gates,
                         const std::vector<Pass>& passes) {
     using V = typename V2T<R>::type;
-    constexpr int KMAX = TileK<R>::value;
-    // layout of the upload: for each tile pass, a header followed by its gates
+    // upload layout: per tile pass, header, stages, gates (256-byte aligned)
     size_t bytes = 0;
     std::vector<size_t> offs(passes.size(), 0);
     for (size_t i = 0; i < passes.size(); ++i) {
         if (passes[i].single) continue;
+        if (passes[i].k < kMinTileBits || passes[i].k > TileK<R>::value || n - passes[i].k > 30)
+            return hipErrorInvalidValue;
         offs[i] = bytes;
-        bytes += sizeof(TPassHdr) + passes[i].gates.size() * sizeof(TGate<R>);
+        bytes += sizeof(TPassHdr) + passes[i].stages.size() * sizeof(TStage) +
+                 passes[i].gates.size() * sizeof(TGate<R>);
         bytes = (bytes + 255) & ~size_t(255);
     }
     char* dev = nullptr;
@@ -205,19 +339,33 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
             if (ps.single) continue;
             TPassHdr* hd = reinterpret_cast<TPassHdr*>(h + offs[i]);
             hd->k = ps.k;
+            hd->nstages = int32_t(ps.stages.size());
             hd->ngates = int32_t(ps.gates.size());
+            hd->pad = 0;
             int loc[64];
             for (int p = 0; p < 64; ++p) loc[p] = -1;
             for (int b = 0; b < 24; ++b) hd->pos[b] = b < ps.k ? ps.pos[b] : 0;
             for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
-            TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + offs[i] + sizeof(TPassHdr));
-            for (size_t gi = 0; gi < ps.gates.size(); ++gi) {
-                const PGate& g = gates[ps.gates[gi]];
-                tg[gi].kind = g.kind;
-                tg[gi].l0 = loc[g.p0];
-                tg[gi].l1 = g.kind == QSV_G1Q ? 0 : loc[g.p1];
-                tg[gi].cs = g.cs;
-                for (int m = 0; m < 32; ++m) tg[gi].m[m] = R(g.m[m]);
+            TStage* ts = reinterpret_cast<TStage*>(h + offs[i] + sizeof(TPassHdr));
+            TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + offs[i] + sizeof(TPassHdr) +
+                                                       ps.stages.size() * sizeof(TStage));
+            int gi = 0;
+            for (size_t si = 0; si < ps.stages.size(); ++si) {
+                const Stage& st = ps.stages[si];
+                ts[si].gbeg = gi;
+                uint32_t used = 0;
+                for (int j = 0; j < 8; ++j) {
+                    ts[si].rbits[j] = j < st.nr ? st.rbits[j] : 0;
+                    if (j < st.nr) used |= 1u << st.rbits[j];
+                }
+                int tj = 0;
+                for (int b = 0; b < ps.k && tj < 8; ++b)
+                    if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
+                for (; tj < 8; ++tj) ts[si].tbits[tj] = 0;
+                for (int g : st.gates)
+                    if (!to_device_gate<R>(gates[size_t(g)], loc, st, tg[gi++]))
+                        return hipErrorInvalidValue;
+                ts[si].gend = gi;
             }
         }
         void* d = nullptr;
@@ -226,20 +374,16 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         dev = static_cast<char*>(d);
     }
     const char* pname = sizeof(R) == 8 ? "tile_pass_c128" : "tile_pass_c64";
+    const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
     for (size_t i = 0; i < passes.size(); ++i) {
         const Pass& ps = passes[i];
         hipError_t e;
         if (ps.single) {
-            e = launch_gate(ctx, s, n, sizeof(R) == 8 ? QSV_C128 : QSV_C64, gates[ps.gates[0]]);
+            e = launch_gate(ctx, s, n, dt, gates[size_t(ps.gates[0])]);
         } else {
-            if (n - ps.k > 30) return hipErrorInvalidConfiguration;   // grid limit
-            const unsigned tiles = unsigned(uint64_t(1) << (n - ps.k));
             prof_before(ctx, pname, 2.0 * double(uint64_t(1) << n) * sizeof(V));
-            hipLaunchKernelGGL((k_tile<R, KMAX>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
-                               static_cast<V*>(s), reinterpret_cast<const TPassHdr*>(dev + offs[i]),
-                               reinterpret_cast<const TGate<R>*>(dev + offs[i] + sizeof(TPassHdr)));
+            e = launch_tile_k<R>(ctx, s, n, ps.k, dev + offs[i]);
             prof_after(ctx);
-            e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
     }

@@ -157,17 +157,22 @@ def test_fused_multi_tile_vs_oracle(q, ctx, n, seed):
     assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
 
 
-@pytest.mark.parametrize("tb,lb", [(4, 0), (6, 2), (8, 3), (10, 5), (12, 3), (12, 8)])
+@pytest.mark.parametrize("tb,lb", [(10, 1), (10, 8), (11, 3), (12, 3), (12, 8), (12, 10)])
 def test_tile_shapes_agree(q, ctx, tb, lb):
     n = 14
     c = W.random_mix(n, 80, seed=tb * 10 + lb)
     ref = O.run(c)
     c2 = q.Context()
     c2.set_tile(q.QSV_C128, tb, lb)
+    c2.set_tile(q.QSV_C64, tb + 1, lb)
     st = make_state(q, c2, n)
     st.apply_circuit(c.gates)
     assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
+    s64 = make_state(q, c2, n, q.QSV_C64)
+    s64.apply_circuit(c.gates)
+    assert infidelity(s64.to_numpy(), ref) <= 1e-6
     st.free()
+    s64.free()
     c2.close()
 
 

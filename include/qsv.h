@@ -244,7 +244,7 @@ qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
 
 /* Tile shape of the context's later fused passes for one dtype.
  * tile_bits: log2 of the amplitudes per tile, in [10, 12] for QSV_C128 and
- * [10, 13] for QSV_C64 (0 = the maximum).  States with fewer than 10 qubits
+ * [10, 13] for QSV_C64 (0 = the default, 12).  States with fewer than 10 qubits
  * run one kernel per gate.  low_bits: number of lowest index
  * bits every tile keeps, so each tile is made of contiguous runs of
  * 2^low_bits amplitudes; in [0, tile_bits - 2] (0 = 3 for QSV_C128, 4 for

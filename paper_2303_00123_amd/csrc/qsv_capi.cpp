@@ -602,7 +602,7 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits) {
     if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
     TileConfig& cfg = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
     const int kmax = tile_bits_max(dtype);
-    const int tb = tile_bits ? tile_bits : kmax;
+    const int tb = tile_bits ? tile_bits : kDefaultTileBits;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
     if (tb < kMinTileBits || tb > kmax)
         return fail(ctx, QSV_ERR_ARG, "tile_bits must be in [" + std::to_string(kMinTileBits) + ", " +
@@ -621,7 +621,7 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
     if (ng < 0 || (ng > 0 && (!g || !pass_of_gate || !exec_order || !pass_qubits)) || !npasses)
         return QSV_ERR_ARG;
     const int kmax = tile_bits_max(dtype);
-    const int tb = tile_bits ? tile_bits : kmax;
+    const int tb = tile_bits ? tile_bits : kDefaultTileBits;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
     if (tb < kMinTileBits || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
     // positions only: rotations get a placeholder angle

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/qsv.h"
+#include "qsv.h"
 
 namespace qsv {
 
@@ -48,6 +48,7 @@ struct TileConfig {
 
 constexpr int kTileThreads = 256;   // threads per tile workgroup (8 thread bits)
 constexpr int kMinTileBits = 10;    // at least 2 register bits per thread
+constexpr int kDefaultTileBits = 12;
 
 // Group gates into passes (greedy, dependency-respecting), then split each
 // tile pass into register stages.
@@ -118,7 +119,7 @@ struct qsv_ctx_s {
     size_t d_aux_doubles = 0;
 
     qsv::TileConfig tile_c128{12, 3};
-    qsv::TileConfig tile_c64{13, 4};
+    qsv::TileConfig tile_c64{12, 4};
 
     // profiling
     bool profiling = false;

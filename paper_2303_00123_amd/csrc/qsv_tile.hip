@@ -151,6 +151,10 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
     }
 }
 
+// Controlled kinds are emitted for control state 1 only (the host lowers a
+// control-state-0 gate to a 2-qubit gate), and 2-qubit gates with r0 < r1
+// (the host permutes the matrix), which keeps the number of compiled
+// specialisations -- and the kernel's instruction footprint -- small.
 template <int RB, typename R, typename V, int P>
 __device__ __forceinline__ void apply_gate(V (&v)[P], const TGate<R>& g) {
     const int kind = g.kind;
@@ -161,26 +165,18 @@ __device__ __forceinline__ void apply_gate(V (&v)[P], const TGate<R>& g) {
     } else if (kind == DK_2Q) {
         on_bit<RB>(g.r0, [&](auto A) __attribute__((always_inline)) {
             on_bit<RB>(g.r1, [&](auto B) __attribute__((always_inline)) {
-                if constexpr (decltype(A)::value != decltype(B)::value)
+                if constexpr (decltype(A)::value < decltype(B)::value)
                     rg_2q<decltype(A)::value, decltype(B)::value>(v, g.m);
             });
         });
     } else {
-        const int cs = g.cs;
         on_bit<RB>(g.r0, [&](auto C) __attribute__((always_inline)) {
             on_bit<RB>(g.r1, [&](auto T) __attribute__((always_inline)) {
                 constexpr int c = decltype(C)::value, t = decltype(T)::value;
                 if constexpr (c != t) {
-                    if (kind == DK_CX) {
-                        if (cs) rg_cx<c, t, 1>(v);
-                        else rg_cx<c, t, 0>(v);
-                    } else if (kind == DK_CD) {
-                        if (cs) rg_cd<c, t, 1>(v, g.m);
-                        else rg_cd<c, t, 0>(v, g.m);
-                    } else {
-                        if (cs) rg_c1q<c, t, 1>(v, g.m);
-                        else rg_c1q<c, t, 0>(v, g.m);
-                    }
+                    if (kind == DK_CX) rg_cx<c, t, 1>(v);
+                    else if (kind == DK_CD) rg_cd<c, t, 1>(v, g.m);
+                    else rg_c1q<c, t, 1>(v, g.m);
                 }
             });
         });
@@ -194,6 +190,9 @@ __device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restric
 }
 
 // ------------------------------------------------------------ the kernel
+// One workgroup per tile.  Every stage record (including the first and the
+// last, which carry the load mapping) drives the same loop body, so the gate
+// dispatch is compiled once.
 template <typename R, int K>
 __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __restrict__ s,
                                                    const char* __restrict__ plan) {
@@ -201,7 +200,9 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
     constexpr int E = 1 << K;
     constexpr int RB = K - 8;
     constexpr int P = 1 << RB;
+    constexpr uint32_t ES = sizeof(V);   // bytes per LDS slot
     __shared__ V tile[E];
+    char* lds = reinterpret_cast<char*>(tile);
 
     const TPassHdr* hdr = reinterpret_cast<const TPassHdr*>(plan);
     const TStage* stg = reinterpret_cast<const TStage*>(plan + sizeof(TPassHdr));
@@ -210,59 +211,73 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
                                                               size_t(nst) * sizeof(TStage));
     const uint32_t tid = threadIdx.x;
 
-    uint64_t base = blockIdx.x;
+    // per-thread pointer to this tile's slot-0 amplitude; slot u adds a
+    // uniform offset (disjoint bits, so OR == ADD)
+    uint64_t b = blockIdx.x;
 #pragma unroll
-    for (int i = 0; i < K; ++i) base = insert0(base, hdr->pos[i]);
-    const uint64_t dt = base | deposit(tid, hdr->pos, 8);
+    for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
+    V* const sp = s + (b | deposit(tid, hdr->pos, 8));
 
     V v[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) v[u] = s[dt | deposit(uint32_t(u), hdr->pos + 8, RB)];
-    apply_range<RB>(v, gates, stg[0].gbeg, stg[0].gend);
+    for (int u = 0; u < P; ++u) v[u] = sp[deposit(uint32_t(u), hdr->pos + 8, RB)];
 
-    if (nst > 1) {
+    for (int st = 0; st < nst; ++st) {
+        const TStage& S = stg[st];
+        // LDS byte address of slot u = swz(eb | du) * ES = (swz(eb) ^ swz(du)) * ES;
+        // the swizzle is XOR-linear, so the thread part is computed once and
+        // the slot part is uniform.
+        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
+        if (st > 0) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) tile[swz<R>(uint32_t(u) * kThreads + tid)] = v[u];
-        __syncthreads();
-        for (int st = 1; st < nst - 1; ++st) {
-            const TStage& S = stg[st];
-            const uint32_t eb = deposit32(tid, S.tbits, 8);
-            uint32_t ea[P];
+            for (int u = 0; u < P; ++u)
+                v[u] = *reinterpret_cast<const V*>(lds + (sb ^ (swz<R>(deposit32(uint32_t(u), S.rbits, RB)) * ES)));
+        }
+        apply_range<RB>(v, gates, S.gbeg, S.gend);
+        if (st < nst - 1) {
 #pragma unroll
-            for (int u = 0; u < P; ++u) {
-                ea[u] = swz<R>(eb | deposit32(uint32_t(u), S.rbits, RB));
-                v[u] = tile[ea[u]];
-            }
-            apply_range<RB>(v, gates, S.gbeg, S.gend);
-#pragma unroll
-            for (int u = 0; u < P; ++u) tile[ea[u]] = v[u];
+            for (int u = 0; u < P; ++u)
+                *reinterpret_cast<V*>(lds + (sb ^ (swz<R>(deposit32(uint32_t(u), S.rbits, RB)) * ES))) = v[u];
             __syncthreads();
         }
-#pragma unroll
-        for (int u = 0; u < P; ++u) v[u] = tile[swz<R>(uint32_t(u) * kThreads + tid)];
-        apply_range<RB>(v, gates, stg[nst - 1].gbeg, stg[nst - 1].gend);
     }
 #pragma unroll
-    for (int u = 0; u < P; ++u) s[dt | deposit(uint32_t(u), hdr->pos + 8, RB)] = v[u];
+    for (int u = 0; u < P; ++u) sp[deposit(uint32_t(u), hdr->pos + 8, RB)] = v[u];
 }
 
 // ------------------------------------------------------------ host side
 bool is_zero(double x) { return x == 0.0; }
 
-// Returns false if a gate bit is not a register bit of its stage (a planner bug).
+// Lower a host gate to the device record of its stage.  Returns false if a
+// gate bit is not a register bit of the stage (a planner bug).
 template <typename R>
 bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t) {
     int reg[32];
     for (int b = 0; b < 32; ++b) reg[b] = -1;
     for (int j = 0; j < st.nr; ++j) reg[st.rbits[j]] = j;
     for (int m = 0; m < 32; ++m) t.m[m] = R(0);
-    t.cs = g.cs;
+    t.cs = 1;
+    if (loc[g.p0] < 0 || (g.kind != QSV_G1Q && loc[g.p1] < 0)) return false;
     t.r0 = reg[loc[g.p0]];
     t.r1 = g.kind == QSV_G1Q ? 0 : reg[loc[g.p1]];
-    if (loc[g.p0] < 0 || t.r0 < 0 || t.r1 < 0 || (g.kind != QSV_G1Q && (loc[g.p1] < 0 || t.r0 == t.r1)))
-        return false;
+    if (t.r0 < 0 || t.r1 < 0 || (g.kind != QSV_G1Q && t.r0 == t.r1)) return false;
     const double* m = g.m;
-    if (g.kind == QSV_G1Q) {
+    double m4[32];
+    int kind = g.kind;
+    if (kind == QSV_GC1Q && g.cs == 0) {
+        // |0><0|_c (x) U + |1><1|_c (x) I on (c, t): a 4x4 in basis 2*x_c + x_t
+        for (int i = 0; i < 32; ++i) m4[i] = 0.0;
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                m4[2 * (4 * r + c)] = m[2 * (2 * r + c)];
+                m4[2 * (4 * r + c) + 1] = m[2 * (2 * r + c) + 1];
+            }
+        m4[2 * (4 * 2 + 2)] = 1.0;
+        m4[2 * (4 * 3 + 3)] = 1.0;
+        m = m4;
+        kind = QSV_G2Q;
+    }
+    if (kind == QSV_G1Q) {
         if (is_zero(m[2]) && is_zero(m[3]) && is_zero(m[4]) && is_zero(m[5])) {
             t.kind = DK_1D;
             t.m[0] = R(m[0]); t.m[1] = R(m[1]); t.m[2] = R(m[6]); t.m[3] = R(m[7]);
@@ -270,7 +285,7 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
             t.kind = DK_1Q;
             for (int i = 0; i < 8; ++i) t.m[i] = R(m[i]);
         }
-    } else if (g.kind == QSV_GC1Q) {
+    } else if (kind == QSV_GC1Q) {
         const bool offzero = is_zero(m[2]) && is_zero(m[3]) && is_zero(m[4]) && is_zero(m[5]);
         const bool is_x = is_zero(m[0]) && is_zero(m[1]) && m[2] == 1.0 && is_zero(m[3]) &&
                           m[4] == 1.0 && is_zero(m[5]) && is_zero(m[6]) && is_zero(m[7]);
@@ -285,7 +300,20 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
         }
     } else {
         t.kind = DK_2Q;
-        for (int i = 0; i < 32; ++i) t.m[i] = R(m[i]);
+        if (t.r0 < t.r1) {
+            for (int i = 0; i < 32; ++i) t.m[i] = R(m[i]);
+        } else {
+            // exchange the two qubits: rows/columns permuted by (0, 2, 1, 3)
+            static const int sg[4] = {0, 2, 1, 3};
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    t.m[2 * (4 * r + c)] = R(m[2 * (4 * sg[r] + sg[c])]);
+                    t.m[2 * (4 * r + c) + 1] = R(m[2 * (4 * sg[r] + sg[c]) + 1]);
+                }
+            const int x = t.r0;
+            t.r0 = t.r1;
+            t.r1 = x;
+        }
     }
     return true;
 }

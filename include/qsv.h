@@ -251,6 +251,18 @@ qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
  * QSV_C64, i.e. 128-byte runs). */
 qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits);
 
+/* Host-only query of the exact gate sequence the tile kernels would apply for
+ * qsv_apply_circuit (no device work; needs no GPU): gates grouped into passes
+ * and register stages, with the 1-qubit gates of a stage multiplied into the
+ * neighbouring 2-qubit gates.  out receives up to `cap` records in execution
+ * order (kind QSV_G1Q, QSV_GC1Q or QSV_G2Q with explicit matrices; rotations
+ * are evaluated with params), pass_of_out[i] the pass of record i (either
+ * output may be NULL); *nout receives the number of records, or the number
+ * needed if cap is too small (then QSV_ERR_SIZE). */
+qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
+                          int64_t nparams, int tile_bits, int low_bits, qsv_gate* out, int64_t cap,
+                          int32_t* pass_of_out, int64_t* nout);
+
 /* Host-only query of the fusion plan qsv_apply_circuit would use for an
  * n-qubit circuit (no device work; needs no GPU).  tile_bits / low_bits as in
  * qsv_set_tile (0 = defaults for dtype).  Outputs, each an array of at least

@@ -427,6 +427,7 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
         return QSV_OK;
     }
     const TileConfig& cfg = st->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    pg = prefuse(pg);
     std::vector<Pass> passes = plan_passes(st->n, pg, cfg);
     HIP_OR_FAIL(ctx, run_passes(ctx, st->ptr, st->n, st->dtype, pg, passes), "tile passes");
     return QSV_OK;
@@ -571,8 +572,9 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
                     HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
             } else {
                 const TileConfig& cfg = psi->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
-                HIP_OR_FAIL(ctx, run_passes(ctx, psi->ptr, n, psi->dtype, fwd,
-                                            plan_passes(n, fwd, cfg)),
+                const std::vector<PGate> fused = prefuse(fwd);
+                HIP_OR_FAIL(ctx, run_passes(ctx, psi->ptr, n, psi->dtype, fused,
+                                            plan_passes(n, fused, cfg)),
                             "forward passes");
             }
         }
@@ -647,6 +649,48 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
     }
     *npasses = int64_t(passes.size());
     return QSV_OK;
+}
+
+qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
+                          int64_t nparams, int tile_bits, int low_bits, qsv_gate* out, int64_t cap,
+                          int32_t* pass_of_out, int64_t* nout) {
+    if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
+    if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
+    if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
+    const int kmax = tile_bits_max(dtype);
+    const int tb = tile_bits ? tile_bits : kDefaultTileBits;
+    const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
+    if (tb < kMinTileBits || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
+    std::vector<PGate> pg;
+    if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
+    if (n >= kMinTileBits) pg = prefuse(pg);
+    std::vector<Pass> passes = plan_passes(n, pg, TileConfig{tb, lb});
+    int64_t k = 0;
+    auto emit = [&](const PGate& x, int32_t p) {
+        if (k < cap) {
+            qsv_gate o{};
+            o.kind = x.kind;
+            o.q0 = pos_of(n, x.p0);
+            o.q1 = x.kind == QSV_G1Q ? 0 : pos_of(n, x.p1);
+            o.ctrl_state = x.cs;
+            o.param = -1;
+            std::memcpy(o.m, x.m, sizeof(o.m));
+            if (out) out[k] = o;
+            if (pass_of_out) pass_of_out[k] = p;
+        }
+        ++k;
+    };
+    for (size_t p = 0; p < passes.size(); ++p) {
+        const Pass& ps = passes[p];
+        if (ps.single || ps.stages.empty()) {
+            for (int gi : ps.gates) emit(pg[size_t(gi)], int32_t(p));
+        } else {
+            for (const Stage& st : ps.stages)
+                for (const PGate& x : fuse_stage(pg, st.gates)) emit(x, int32_t(p));
+        }
+    }
+    *nout = k;
+    return k > cap ? QSV_ERR_SIZE : QSV_OK;
 }
 
 // ---------------------------------------------------------------- profiling

@@ -40,14 +40,16 @@ __device__ __forceinline__ void mv2(const R* u, const V& a, const V& b, V& oa, V
     ob.y = u[4] * a.y + u[5] * a.x + u[6] * b.y + u[7] * b.x;
 }
 
-// o[r] = sum_c U[r][c] v[c] for a 4x4 complex U.
+// o[r] = sum_c U[r][c] v[c] for a 4x4 complex U (accumulation starts from
+// the first product, so every term is one multiply-add).
 template <typename R, typename V>
 __device__ __forceinline__ void mv4(const R* u, const V* v, V* o) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        R re = 0, im = 0;
+        R re = u[8 * r] * v[0].x - u[8 * r + 1] * v[0].y;
+        R im = u[8 * r] * v[0].y + u[8 * r + 1] * v[0].x;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 1; c < 4; ++c) {
             const R ur = u[2 * (4 * r + c)], ui = u[2 * (4 * r + c) + 1];
             re += ur * v[c].x - ui * v[c].y;
             im += ur * v[c].y + ui * v[c].x;

@@ -54,6 +54,17 @@ constexpr int kDefaultTileBits = 12;
 // tile pass into register stages.
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg);
 
+// Fuse the gates of one register stage (indices into `gates`, in execution
+// order): 1-qubit gates are multiplied into the next 2-qubit or controlled
+// gate on the same qubit (or emitted at the end of the stage), and a 2-qubit
+// gate directly following another on the same pair is merged into it.  The
+// result applies the same operator with fewer kernel dispatches.
+std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector<int>& idx);
+
+// The same fusion over a whole circuit, applied before pass planning when the
+// state is large enough for tile passes (below that, gates run one by one).
+std::vector<PGate> prefuse(const std::vector<PGate>& gates);
+
 // Device-side gate kinds inside a tile pass.
 enum {
     DK_1Q = 0,    // generic 2x2 on register bit r0
@@ -76,8 +87,8 @@ struct TGate {
 // Stage record in device memory.
 struct TStage {
     int32_t gbeg, gend;     // gate range [gbeg, gend) of the pass's gate array
-    int32_t rbits[8];       // register bit j <-> local bit
     int32_t tbits[8];       // thread-id bit j <-> local bit
+    uint32_t su[32];        // byte offset (after the LDS swizzle) of register slot u
 };
 
 // Pass header in device memory; followed by nstages TStage records and then
@@ -88,7 +99,16 @@ struct TPassHdr {
     int32_t ngates;
     int32_t pad;
     int32_t pos[24];
+    uint64_t du[32];        // amplitude offset of register slot u in the load mapping
 };
+
+// LDS slot swizzle of the tile kernels: an XOR of the slot index with a fold
+// of its higher bits into the bank-selecting low bits.  It is linear over
+// GF(2), so swz(a | b) = swz(a) ^ swz(b) for disjoint a, b.
+__host__ __device__ inline uint32_t tile_swz(uint32_t e, int elem_bytes) {
+    return elem_bytes == 16 ? e ^ (((e >> 4) ^ (e >> 8)) & 15u)
+                            : e ^ (((e >> 5) ^ (e >> 10)) & 31u);
+}
 
 // ------------------------------------------------------------- profiling
 struct ProfRec {

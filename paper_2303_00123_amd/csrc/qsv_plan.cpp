@@ -20,6 +20,8 @@
 // the load mapping so the store is coalesced.  The same greedy, blocking
 // rule orders gates across stages.
 #include <algorithm>
+#include <complex>
+#include <cstring>
 
 #include "qsv_internal.h"
 
@@ -119,6 +121,163 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     }
     for (auto& m : middle) ps.stages.push_back(std::move(m));
     ps.stages.push_back(std::move(last));
+}
+
+
+// ------------------------------------------------------------ stage fusion
+namespace {
+
+using cd = std::complex<double>;
+
+struct M4 { cd a[16]; };   // 4x4 row-major, basis 2*x_hi + x_lo of (qa, qb)
+
+M4 m4_from(const double* m) {
+    M4 r;
+    for (int i = 0; i < 16; ++i) r.a[i] = cd(m[2 * i], m[2 * i + 1]);
+    return r;
+}
+void m4_to(const M4& x, double* m) {
+    for (int i = 0; i < 16; ++i) {
+        m[2 * i] = x.a[i].real();
+        m[2 * i + 1] = x.a[i].imag();
+    }
+}
+M4 mul(const M4& x, const M4& y) {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cd acc = 0;
+            for (int k = 0; k < 4; ++k) acc += x.a[4 * i + k] * y.a[4 * k + j];
+            r.a[4 * i + j] = acc;
+        }
+    return r;
+}
+// A (x) B for 2x2 A (first qubit) and B (second)
+M4 kron(const cd* A, const cd* B) {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.a[4 * i + j] = A[2 * (i >> 1) + (j >> 1)] * B[2 * (i & 1) + (j & 1)];
+    return r;
+}
+// exchange the roles of the two qubits: permute rows/columns by (0, 2, 1, 3)
+M4 swapq(const M4& x) {
+    static const int sg[4] = {0, 2, 1, 3};
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.a[4 * i + j] = x.a[4 * sg[i] + sg[j]];
+    return r;
+}
+void m2_from(const double* m, cd* u) {
+    for (int i = 0; i < 4; ++i) u[i] = cd(m[2 * i], m[2 * i + 1]);
+}
+void m2_mul(const cd* x, const cd* y, cd* r) {   // r = x y
+    cd t[4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) t[2 * i + j] = x[2 * i] * y[j] + x[2 * i + 1] * y[2 + j];
+    for (int i = 0; i < 4; ++i) r[i] = t[i];
+}
+
+// the 4x4 of a 2-position gate in the basis 2*x_p0 + x_p1
+M4 as4(const PGate& g) {
+    if (g.kind == QSV_G2Q) return m4_from(g.m);
+    // controlled: |~cs><~cs| (x) I + |cs><cs| (x) U on (control = p0, target = p1)
+    M4 r;
+    for (int i = 0; i < 16; ++i) r.a[i] = 0;
+    cd u[4];
+    m2_from(g.m, u);
+    const int c1 = g.cs, c0 = 1 - g.cs;
+    r.a[4 * (2 * c0) + 2 * c0] = 1;
+    r.a[4 * (2 * c0 + 1) + 2 * c0 + 1] = 1;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) r.a[4 * (2 * c1 + i) + 2 * c1 + j] = u[2 * i + j];
+    return r;
+}
+
+}  // namespace
+
+std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector<int>& idx) {
+    std::vector<PGate> out;
+    bool has[64] = {false};
+    cd pend[64][4];
+    // index in `out` of the last emitted gate touching each position (-1: none)
+    int last[64];
+    for (int p = 0; p < 64; ++p) last[p] = -1;
+
+    for (int gi : idx) {
+        const PGate& g = gates[size_t(gi)];
+        if (g.kind == QSV_G1Q) {
+            cd u[4];
+            m2_from(g.m, u);
+            if (has[g.p0]) m2_mul(u, pend[g.p0], pend[g.p0]);
+            else {
+                for (int i = 0; i < 4; ++i) pend[g.p0][i] = u[i];
+                has[g.p0] = true;
+            }
+            continue;
+        }
+        const int a = g.p0, b = g.p1;
+        const bool absorb = has[a] || has[b];
+        // merge with the previous gate if it is the last one on both positions
+        // and acts on exactly this pair
+        int prev = -1;
+        if (last[a] >= 0 && last[a] == last[b]) {
+            const PGate& o = out[size_t(last[a])];
+            if (o.kind != QSV_G1Q && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a))) prev = last[a];
+        }
+        if (!absorb && prev < 0) {
+            out.push_back(g);
+            last[a] = last[b] = int(out.size()) - 1;
+            continue;
+        }
+        M4 M = as4(g);   // basis (a, b)
+        if (absorb) {
+            static const cd I2[4] = {1, 0, 0, 1};
+            const cd* ua = has[a] ? pend[a] : I2;
+            const cd* ub = has[b] ? pend[b] : I2;
+            M = mul(M, kron(ua, ub));
+            has[a] = has[b] = false;
+        }
+        if (prev >= 0) {
+            PGate& o = out[size_t(prev)];
+            M4 P = as4(o);
+            if (o.p0 != a) P = swapq(P);   // express the earlier gate in basis (a, b)
+            M = mul(M, P);
+            o.kind = QSV_G2Q;
+            o.p0 = a;
+            o.p1 = b;
+            o.cs = 1;
+            m4_to(M, o.m);
+        } else {
+            PGate f{};
+            f.kind = QSV_G2Q;
+            f.p0 = a;
+            f.p1 = b;
+            f.cs = 1;
+            m4_to(M, f.m);
+            out.push_back(f);
+            last[a] = last[b] = int(out.size()) - 1;
+        }
+    }
+    for (int p = 0; p < 64; ++p)
+        if (has[p]) {
+            PGate f{};
+            f.kind = QSV_G1Q;
+            f.p0 = p;
+            f.p1 = 0;
+            f.cs = 1;
+            for (int i = 0; i < 4; ++i) {
+                f.m[2 * i] = pend[p][i].real();
+                f.m[2 * i + 1] = pend[p][i].imag();
+            }
+            out.push_back(f);
+        }
+    return out;
+}
+
+std::vector<PGate> prefuse(const std::vector<PGate>& gates) {
+    std::vector<int> all(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) all[i] = int(i);
+    return fuse_stage(gates, all);
 }
 
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {

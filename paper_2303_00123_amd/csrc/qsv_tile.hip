@@ -34,14 +34,8 @@ template <>
 struct TileK<float> { static constexpr int value = 13; };    // 8192 x 8 B = 64 KiB
 
 template <typename R>
-__device__ __forceinline__ uint32_t swz(uint32_t e);
-template <>
-__device__ __forceinline__ uint32_t swz<double>(uint32_t e) {
-    return e ^ (((e >> 4) ^ (e >> 8)) & 15u);
-}
-template <>
-__device__ __forceinline__ uint32_t swz<float>(uint32_t e) {
-    return e ^ (((e >> 5) ^ (e >> 10)) & 31u);
+__device__ __forceinline__ uint32_t swz(uint32_t e) {
+    return tile_swz(e, int(sizeof(typename V2T<R>::type)));
 }
 
 // Deposit the low `k` bits of e at the positions pos[0..k).
@@ -192,7 +186,7 @@ __device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restric
 // ------------------------------------------------------------ the kernel
 // One workgroup per tile.  Every stage record (including the first and the
 // last, which carry the load mapping) drives the same loop body, so the gate
-// dispatch is compiled once.
+// dispatch is compiled once.  Slot offsets come precomputed in the plan.
 template <typename R, int K>
 __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __restrict__ s,
                                                    const char* __restrict__ plan) {
@@ -211,8 +205,8 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
                                                               size_t(nst) * sizeof(TStage));
     const uint32_t tid = threadIdx.x;
 
-    // per-thread pointer to this tile's slot-0 amplitude; slot u adds a
-    // uniform offset (disjoint bits, so OR == ADD)
+    // per-thread pointer to this tile's slot-0 amplitude; slot u adds the
+    // uniform offset du[u] (disjoint bits, so OR == ADD)
     uint64_t b = blockIdx.x;
 #pragma unroll
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
@@ -220,29 +214,25 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
 
     V v[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) v[u] = sp[deposit(uint32_t(u), hdr->pos + 8, RB)];
+    for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
 
     for (int st = 0; st < nst; ++st) {
         const TStage& S = stg[st];
-        // LDS byte address of slot u = swz(eb | du) * ES = (swz(eb) ^ swz(du)) * ES;
-        // the swizzle is XOR-linear, so the thread part is computed once and
-        // the slot part is uniform.
+        // LDS byte address of slot u = swz(eb | du) * ES = swz(eb) * ES ^ su[u]
         const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
         if (st > 0) {
 #pragma unroll
-            for (int u = 0; u < P; ++u)
-                v[u] = *reinterpret_cast<const V*>(lds + (sb ^ (swz<R>(deposit32(uint32_t(u), S.rbits, RB)) * ES)));
+            for (int u = 0; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sb ^ S.su[u]));
         }
         apply_range<RB>(v, gates, S.gbeg, S.gend);
         if (st < nst - 1) {
 #pragma unroll
-            for (int u = 0; u < P; ++u)
-                *reinterpret_cast<V*>(lds + (sb ^ (swz<R>(deposit32(uint32_t(u), S.rbits, RB)) * ES))) = v[u];
+            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su[u])) = v[u];
             __syncthreads();
         }
     }
 #pragma unroll
-    for (int u = 0; u < P; ++u) sp[deposit(uint32_t(u), hdr->pos + 8, RB)] = v[u];
+    for (int u = 0; u < P; ++u) sp[hdr->du[u]] = v[u];
 }
 
 // ------------------------------------------------------------ host side
@@ -374,6 +364,14 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
             for (int p = 0; p < 64; ++p) loc[p] = -1;
             for (int b = 0; b < 24; ++b) hd->pos[b] = b < ps.k ? ps.pos[b] : 0;
             for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
+            const int rb = ps.k - 8;
+            for (int u = 0; u < 32; ++u) {
+                uint64_t off = 0;
+                if (u < (1 << rb))
+                    for (int j = 0; j < rb; ++j)
+                        if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[8 + j];
+                hd->du[u] = off;
+            }
             TStage* ts = reinterpret_cast<TStage*>(h + offs[i] + sizeof(TPassHdr));
             TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + offs[i] + sizeof(TPassHdr) +
                                                        ps.stages.size() * sizeof(TStage));
@@ -382,17 +380,20 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
                 const Stage& st = ps.stages[si];
                 ts[si].gbeg = gi;
                 uint32_t used = 0;
-                for (int j = 0; j < 8; ++j) {
-                    ts[si].rbits[j] = j < st.nr ? st.rbits[j] : 0;
-                    if (j < st.nr) used |= 1u << st.rbits[j];
-                }
+                for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
                 int tj = 0;
                 for (int b = 0; b < ps.k && tj < 8; ++b)
                     if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
                 for (; tj < 8; ++tj) ts[si].tbits[tj] = 0;
-                for (int g : st.gates)
-                    if (!to_device_gate<R>(gates[size_t(g)], loc, st, tg[gi++]))
-                        return hipErrorInvalidValue;
+                for (int u = 0; u < 32; ++u) {
+                    uint32_t e = 0;
+                    if (u < (1 << st.nr))
+                        for (int j = 0; j < st.nr; ++j)
+                            if ((u >> j) & 1) e |= 1u << st.rbits[j];
+                    ts[si].su[u] = tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
+                }
+                for (const PGate& fg : fuse_stage(gates, st.gates))
+                    if (!to_device_gate<R>(fg, loc, st, tg[gi++])) return hipErrorInvalidValue;
                 ts[si].gend = gi;
             }
         }

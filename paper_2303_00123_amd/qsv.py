@@ -44,7 +44,7 @@ EXPORTS = [
     "qsv_init_basis", "qsv_apply1q", "qsv_applyC1q", "qsv_apply2q", "qsv_apply_circuit",
     "qsv_norm2", "qsv_expect_z", "qsv_inner", "qsv_prob1", "qsv_measure1", "qsv_copy_to_host",
     "qsv_copy_from_host", "qsv_adjoint", "qsv_batch_run", "qsv_profile_begin", "qsv_profile_end",
-    "qsv_set_tile", "qsv_plan_circuit",
+    "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused",
 ]
 
 
@@ -96,6 +96,7 @@ def lib():
         "qsv_profile_end": [vp, vp, i32, P(i32)],
         "qsv_set_tile": [vp, i32, i32, i32],
         "qsv_plan_circuit": [i32, i32, vp, i64, i32, i32, P(i64), vp, vp, vp],
+        "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, vp, i64, vp, P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -344,6 +345,23 @@ def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_b
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_circuit failed")
     return pog[:ng], order[:ng], pq[: npass.value]
+
+
+def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int = 0,
+               low_bits: int = 0):
+    """Host-only: the exact gate records the kernels apply, in order, and the
+    pass index of each (see qsv_plan_fused)."""
+    g = marshal_gates(gates)
+    p = np.ascontiguousarray(np.zeros(0) if params is None else params, dtype=np.float64)
+    cap = 2 * len(g) + 8
+    out = np.zeros(cap, dtype=GATE_DTYPE)
+    pas = np.zeros(cap, dtype=np.int32)
+    nout = ctypes.c_int64()
+    st = lib().qsv_plan_fused(n, dtype, _ptr(g), len(g), _ptr(p), p.size, tile_bits, low_bits,
+                              _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
+    if st != QSV_OK:
+        raise QsvError(st, "qsv_plan_fused failed")
+    return out[: nout.value], pas[: nout.value]
 
 
 def adjoint(psi: State, lam: State, gates, params, obs, flags: int = FLAG_FORWARD,

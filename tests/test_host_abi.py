@@ -137,3 +137,47 @@ def test_planner_below_min_tile_runs_gate_by_gate():
     assert len(pq) == 30 and list(order) == list(range(30))
     with pytest.raises(q.QsvError):
         q.plan_circuit(14, c.gates, q.QSV_C128, 9, 0)
+
+
+# ------------------------------------------------------------ fused sequence
+def _records_to_circuit(n, recs):
+    """qsv_gate records (explicit matrices) -> a workloads circuit."""
+    gates = []
+    for r in recs:
+        m = r["m"][0::2] + 1j * r["m"][1::2]
+        if r["kind"] == q.qsv.G1Q:
+            gates.append(W.g1(int(r["q0"]), m[:4].reshape(2, 2)))
+        elif r["kind"] == q.qsv.GC1Q:
+            gates.append(W.gc(int(r["q0"]), int(r["q1"]), m[:4].reshape(2, 2), int(r["ctrl_state"])))
+        else:
+            gates.append(W.g2(int(r["q0"]), int(r["q1"]), m.reshape(4, 4)))
+    return W.Circuit(n, gates)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.random_mix(14, 200, seed=5),
+    lambda: W.layered_cnot_brick(16, 6, seed=6),
+    lambda: W.layered_haar_pairs(15, 4, seed=7),
+    lambda: W.hea_cz_ring(13, 3, seed=8),
+    lambda: W.qft(12),
+    lambda: W.config1(),
+])
+@pytest.mark.parametrize("dtype,tb,lb", [(q.QSV_C128, 0, 0), (q.QSV_C128, 10, 2), (q.QSV_C64, 12, 4),
+                                         (q.QSV_C64, 13, 0)])
+def test_fused_sequence_equals_circuit(maker, dtype, tb, lb):
+    """The planner + stage fusion (host logic) produce a gate sequence whose
+    product equals the circuit: the oracle runs both."""
+    c = maker()
+    recs, pas = q.plan_fused(c.n, c.gates, c.params, dtype, tb, lb)
+    assert len(recs) <= len(c.gates)
+    assert np.all(np.diff(pas) >= 0)
+    phi = W.random_state(c.n, 11)
+    got = O.run(_records_to_circuit(c.n, recs), phi)
+    ref = O.run(c, phi)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_fusion_reduces_dispatches_on_brick_circuit():
+    c = W.layered_cnot_brick(30, 20, seed=3002)
+    recs, pas = q.plan_fused(c.n, c.gates)
+    assert len(recs) < 0.7 * len(c.gates)

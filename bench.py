@@ -81,6 +81,20 @@ def kernel_roofline(prof: dict, name: str):
             "bytes_per_launch": per_launch_bytes}
 
 
+def measured_traffic(n: int):
+    """HBM bytes per tile-pass launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, if it was measured on the current kernel sources and workload."""
+    path = os.path.join(ROOT, "profiles", f"traffic_tile_pass_c128_n{n}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2303_00123_amd import profsum
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != profsum.source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def unfused_sweep(q, W, n: int):
     """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3)."""
     import numpy as np
@@ -216,6 +230,8 @@ def main():
     r = primary(q, W, args.n, q.QSV_C128, args.steps, args.warmup)
     value = r["gates"] * args.steps / r["seconds"]
     roof = kernel_roofline(r["prof"], "tile_pass_c128")
+    if roof is not None:
+        roof["traffic"] = measured_traffic(args.n)
     log(f"primary: {value:.1f} gates/s, roofline {roof}")
     extras = {"norm_after": r["norm"], "zz_0_last": r["zz"],
               "kernels_c128": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}

@@ -13,7 +13,8 @@ Also reported (same JSON line):
                 only (time-bounded sample), on this host's cores
   extras        complex64 throughput of the same circuit; unfused per-gate
                 kernel bandwidth; adjoint-gradient / forward time ratio on a
-                24-qubit ansatz (10 layers RY,RZ + CZ ring, 480 parameters)
+                24-qubit ansatz (10 layers RY,RZ + CZ ring, 480 parameters);
+                a 256-circuit batch (12..20 qubits) in one persistent launch
 """
 from __future__ import annotations
 
@@ -165,6 +166,34 @@ def adjoint_ratio(q, W, n: int = 24, layers: int = 10, dtype=None, reps: int = 3
             "adjoint_over_forward": round(tb / tf, 3)}
 
 
+def batch_bench(q, W, dtype, reps: int = 5):
+    """256 parametrised circuits (12..20 qubits, 6 layers RY RZ + CNOT ladder)
+    in one persistent launch: wall time per call (host planning included) and
+    the kernel time of the replayed hipGraph."""
+    import torch
+    circs = W.config4()
+    ctx = q.Context()
+    ctx.batch_run(circs, dtype, flags=q.FLAG_TUNE)
+    ctx.batch_run(circs, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.batch_run(circs, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    ctx.close()
+    name = "batch_graph_c128" if dtype == q.QSV_C128 else "batch_graph_c64"
+    k = prof.get(name, {"launches": 1, "ms": float("nan")})
+    gpu_ms = k["ms"] / max(k["launches"], 1)
+    wall_ms = (t1 - t0) / reps * 1e3
+    return {"workload": "256 circuits, 12..20 qubits, 6 layers RY RZ + CNOT ladder, <sum Z_i>",
+            "circuits": len(circs), "wall_ms_per_batch": round(wall_ms, 3),
+            "graph_ms_per_batch": round(gpu_ms, 3),
+            "circuits_per_s_wall": round(len(circs) / (wall_ms / 1e3), 1),
+            "circuits_per_s_gpu": round(len(circs) / (gpu_ms / 1e3), 1)}
+
+
 def cpu_baseline(W, n: int, budget_s: float = 15.0):
     import numpy as np
     import oracle as O
@@ -245,6 +274,9 @@ def main():
         extras["unfused_c128"] = unfused_sweep(q, W, args.n)
         log("extras: adjoint ratio")
         extras["adjoint"] = adjoint_ratio(q, W)
+        log("extras: batch")
+        extras["batch_c128"] = batch_bench(q, W, q.QSV_C128)
+        extras["batch_c64"] = batch_bench(q, W, q.QSV_C64)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")

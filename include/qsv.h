@@ -76,7 +76,8 @@ enum { QSV_AXIS_X = 0, QSV_AXIS_Y = 1, QSV_AXIS_Z = 2 };
 enum {
     QSV_FLAG_NO_FUSE = 1,        /* one kernel per gate (Algs. 1-3 unfused)          */
     QSV_FLAG_FORWARD = 2,        /* qsv_adjoint: run the circuit from |0...0> first  */
-    QSV_FLAG_CAPTURE_GRAPH = 4   /* qsv_batch_run: capture and replay a hipGraph     */
+    QSV_FLAG_CAPTURE_GRAPH = 4,  /* qsv_batch_run: capture and replay a hipGraph     */
+    QSV_FLAG_TUNE = 8            /* qsv_batch_run: autotune the tile shape            */
 };
 
 typedef struct qsv_ctx_s* qsv_ctx;
@@ -222,11 +223,20 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
  * nq[b] qubits (1 <= nq[b] <= 24), gates g[gate_off[b] .. gate_off[b+1]),
  * rotation angles from params (indices global to the batch), starts in
  * |0..0> and yields out[b] = sum over terms t in [term_off[b], term_off[b+1])
- * of w[t] <Z^{qmasks[t]}>.  dtype selects the state precision
- * (accumulation is FP64 either way).  The library keeps the states in its
- * own scratch memory.  QSV_FLAG_CAPTURE_GRAPH captures the launch sequence in
- * a hipGraph on first use and replays it on later calls with the same batch
- * shape.  Synchronises before returning. */
+ * of w[t] <Z^{qmasks[t]}> (qubit masks relative to circuit b; w may be NULL
+ * for weights 1).  gate_off and term_off have nb + 1 entries starting at 0.
+ * dtype selects the state precision (accumulation is FP64 either way).  Each
+ * circuit is applied with the fused tile passes of qsv_apply_circuit; the
+ * library keeps the multi-pass states in its own device memory, and states
+ * of one tile never leave the workgroup.
+ * QSV_FLAG_TUNE: on the first call for a batch shape (qubit counts, gate
+ * kinds and qubits, observable terms -- not the angles) time each candidate
+ * tile shape once and keep the fastest for later calls (file cache if the
+ * environment variable QSV_TUNE_CACHE names one).
+ * QSV_FLAG_CAPTURE_GRAPH: capture upload, counter reset, kernel and result
+ * download in a hipGraph on a library-owned stream, and replay it on later
+ * calls with the same batch shape (new angles are uploaded by the replay).
+ * Synchronises before returning. */
 qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off,
                          const qsv_gate* g, const double* params, int64_t nparams,
                          const int64_t* term_off, const uint64_t* qmasks, const double* w,

@@ -29,6 +29,7 @@ SOURCES = [
     "qsv_tile.hip",
     "qsv_adjoint.hip",
     "qsv_batch.hip",
+    "qsv_tune.cpp",
 ]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.

@@ -1,13 +1,716 @@
-// Batched persistent launch (placeholder until the persistent kernel lands).
-#include "qsv_internal.h"
+// Batched persistent launch: many independent circuits (different qubit
+// counts, gates and angles) in one kernel launch.
+//
+// Every circuit is planned like a single state (fused tile passes of 2^K
+// amplitudes, register stages, gate fusion); a circuit narrower than K
+// qubits is padded with idle qubits at the low index bits, so its whole
+// state is one tile.  The launch processes a work list of items (circuit,
+// pass, tile) that workgroups claim with an atomic counter:
+//   * a circuit's first pass builds |0...0> in registers instead of loading;
+//   * its last pass reduces sum_t w_t <Z^{m_t}> over the tile (FP64) instead
+//     of storing the state; the workgroup finishing the circuit's last tile
+//     adds the per-tile partials in tile order and writes out[b];
+//   * a single-tile circuit (first == last pass) never touches HBM.
+// Items are listed pass-level-major, so an item of pass p only ever waits
+// for items of pass p-1 of its circuit, all of which were claimed earlier by
+// running workgroups: the wait always ends, whatever the number of resident
+// workgroups.  Waits are still bounded: past a spin limit the kernel raises
+// an error flag and drains the queue without computing.
+//
+// HBM states of different circuits never alias; cross-workgroup visibility
+// (the per-XCD L2s are not coherent with each other) uses agent-scope
+// release/acquire on the per-circuit completion counters.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+
+#include "qsv_tile_core.h"
+
+namespace qsv {
+namespace {
+
+using namespace tile;
+
+enum { BP_FIRST = 1, BP_LAST = 2 };
+
+struct BCirc {
+    uint64_t state_off;   // amplitude offset of the circuit's state (multi-pass circuits)
+    uint64_t part_off;    // offset of its per-tile partial sums
+    int32_t tiles;        // tiles per pass
+    int32_t npasses;
+    int32_t term_beg, term_end;
+};
+
+struct BPass {
+    int32_t circ;
+    int32_t level;
+    uint32_t rec_off;     // byte offset of the pass record in the plan
+    int32_t flags;
+};
+
+struct BItem {
+    int32_t pass;
+    int32_t tile;
+};
+
+// counters layout (uint32): [0] next item, [1] error flag, [2 ..) done per circuit
+constexpr int kCtrDone = 2;
+
+__device__ __forceinline__ double zsign_sum(uint64_t x, const uint64_t* __restrict__ m,
+                                            const double* __restrict__ w, int beg, int end) {
+    double d = 0.0;
+    for (int t = beg; t < end; ++t) d += (__popcll(x & m[t]) & 1) ? -w[t] : w[t];
+    return d;
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __restrict__ states,
+                                                    const char* __restrict__ plan,
+                                                    const BCirc* __restrict__ circs,
+                                                    const BPass* __restrict__ passes,
+                                                    const BItem* __restrict__ items, int nitems,
+                                                    const uint64_t* __restrict__ tmask,
+                                                    const double* __restrict__ tw,
+                                                    unsigned* __restrict__ ctr,
+                                                    double* __restrict__ partials,
+                                                    double* __restrict__ out, unsigned spin_limit) {
+    using V = typename V2T<R>::type;
+    constexpr int E = 1 << K;
+    constexpr int RB = K - 8;
+    constexpr int P = 1 << RB;
+    __shared__ V tile[E];
+    __shared__ double red[1][kThreads];
+    __shared__ int s_item;
+    __shared__ int s_flag;
+    char* lds = reinterpret_cast<char*>(tile);
+    const uint32_t tid = threadIdx.x;
+
+    for (;;) {
+        if (tid == 0) s_item = int(atomicAdd(&ctr[0], 1u));
+        __syncthreads();
+        const int it = s_item;
+        if (it >= nitems) return;   // uniform: every wave of the workgroup leaves
+        const BItem I = items[it];
+        const BPass Pp = passes[I.pass];
+        const BCirc C = circs[Pp.circ];
+        const TPassHdr* hdr = reinterpret_cast<const TPassHdr*>(plan + Pp.rec_off);
+        const int nst = hdr->nstages;
+        const TStage* stg = reinterpret_cast<const TStage*>(plan + Pp.rec_off + sizeof(TPassHdr));
+        const TGate<R>* gates = reinterpret_cast<const TGate<R>*>(
+            plan + Pp.rec_off + sizeof(TPassHdr) + size_t(nst) * sizeof(TStage));
+
+        uint64_t b = uint32_t(I.tile);
+#pragma unroll
+        for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
+        const uint64_t xt = b | deposit(tid, hdr->pos, 8);   // index of register slot 0
+        V* const sp = states + C.state_off + xt;
+
+        V v[P];
+        bool ok = true;
+        if (Pp.flags & BP_FIRST) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                v[u].x = (xt | hdr->du[u]) == 0 ? R(1) : R(0);
+                v[u].y = R(0);
+            }
+        } else {
+            // wait until every tile of the circuit's previous pass is stored
+            if (tid == 0) {
+                const unsigned need = unsigned(Pp.level) * unsigned(C.tiles);
+                unsigned spins = 0;
+                int flag = 0;
+                while (__hip_atomic_load(&ctr[kCtrDone + Pp.circ], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                        ++spins > spin_limit) {
+                        atomicOr(&ctr[1], 1u);
+                        flag = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                s_flag = flag;
+            }
+            __syncthreads();
+            ok = s_flag == 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (ok) {
+#pragma unroll
+                for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
+            }
+        }
+        if (ok) run_stages<R, K>(v, lds, stg, nst, gates, tid);
+
+        if (Pp.flags & BP_LAST) {
+            double acc = 0.0;
+            if (ok) {
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    const double re = double(v[u].x), im = double(v[u].y);
+                    acc += (re * re + im * im) *
+                           zsign_sum(xt | hdr->du[u], tmask, tw, C.term_beg, C.term_end);
+                }
+            }
+            red[0][tid] = acc;
+            double tot[1];
+            block_tree256<1>(red, tot);
+            if (tid == 0) {
+                if (C.tiles == 1 && C.npasses == 1) {
+                    out[Pp.circ] = tot[0];
+                } else {
+                    partials[C.part_off + uint32_t(I.tile)] = tot[0];
+                    const unsigned total = unsigned(C.npasses) * unsigned(C.tiles);
+                    const unsigned prev = __hip_atomic_fetch_add(&ctr[kCtrDone + Pp.circ], 1u,
+                                                                 __ATOMIC_ACQ_REL,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    if (prev + 1 == total) {   // last tile of the circuit: fixed-order sum
+                        double s = 0.0;
+                        for (int t = 0; t < C.tiles; ++t) s += partials[C.part_off + t];
+                        out[Pp.circ] = s;
+                    }
+                }
+            }
+        } else {
+            if (ok) {
+#pragma unroll
+                for (int u = 0; u < P; ++u) sp[hdr->du[u]] = v[u];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&ctr[kCtrDone + Pp.circ], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();   // s_item / LDS reuse by the next item
+    }
+}
+
+// zero n words (a kernel rather than a memset, so the sequence can be captured)
+__global__ void k_zero(unsigned* __restrict__ p, size_t n) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+inline int pos_in(int n, int q) { return n - 1 - q; }
+
+struct BatchBuild {
+    std::vector<char> plan;
+    std::vector<BCirc> circs;
+    std::vector<BPass> passes;
+    std::vector<BItem> items;
+    std::vector<uint64_t> tmask;
+    std::vector<double> tw;
+    uint64_t state_amps = 0;
+    uint64_t partial_count = 0;
+    uint64_t shape_key = 1469598103934665603ull;
+};
+
+void mix(uint64_t& h, uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+        h ^= (v >> (8 * i)) & 0xff;
+        h *= 1099511628211ull;
+    }
+}
+
+// Plan every circuit and lay out the device tables.  Returns an error text
+// on invalid input ("" on success).
+std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
+                        const double* params, int64_t nparams, const int64_t* term_off,
+                        const uint64_t* qmasks, const double* w, int dtype, int K, int L,
+                        BatchBuild& B) {
+    const size_t amp = amp_bytes(dtype);
+    std::vector<std::vector<Pass>> plans(static_cast<size_t>(nb));
+    std::vector<std::vector<PGate>> lowered(static_cast<size_t>(nb));
+    mix(B.shape_key, uint64_t(nb));
+    mix(B.shape_key, uint64_t(dtype));
+    int maxp = 0;
+    for (int c = 0; c < nb; ++c) {
+        const int n = nq[c];
+        const int ne = n < K ? K : n;
+        const int64_t g0 = gate_off[c], g1 = gate_off[c + 1];
+        std::vector<PGate>& pg = lowered[size_t(c)];
+        for (int64_t i = g0; i < g1; ++i) {
+            const qsv_gate& G = g[i];
+            PGate p{};
+            const std::string at = "circuit " + std::to_string(c) + " gate " + std::to_string(i - g0) + ": ";
+            const bool two = G.kind == QSV_GC1Q || G.kind == QSV_G2Q;
+            if (G.kind < QSV_G1Q || G.kind > QSV_GROT) return at + "unknown kind";
+            if (G.q0 < 0 || G.q0 >= n || (two && (G.q1 < 0 || G.q1 >= n || G.q1 == G.q0)))
+                return at + "bad qubit";
+            mix(B.shape_key, uint64_t(G.kind) | (uint64_t(G.q0) << 8) | (uint64_t(two ? G.q1 : 0) << 16) |
+                                 (uint64_t(G.ctrl_state & 1) << 24) | (uint64_t(G.axis & 3) << 26));
+            p.kind = G.kind == QSV_GROT ? QSV_G1Q : G.kind;
+            p.p0 = pos_in(ne, G.q0);
+            p.p1 = two ? pos_in(ne, G.q1) : 0;
+            p.cs = G.ctrl_state;
+            if (G.kind == QSV_GC1Q && G.ctrl_state != 0 && G.ctrl_state != 1) return at + "bad control state";
+            if (G.kind == QSV_GROT) {
+                if (G.axis < 0 || G.axis > 2) return at + "bad axis";
+                if (G.param < 0 || G.param >= nparams) return at + "parameter index out of range";
+                rotation_matrix(G.axis, params[G.param], p.m);
+            } else {
+                std::memcpy(p.m, G.m, sizeof(double) * (G.kind == QSV_G2Q ? 32 : 8));
+            }
+            pg.push_back(p);
+        }
+        pg = prefuse(pg);
+        plans[size_t(c)] = plan_passes(ne, pg, TileConfig{K, L});
+        // a pass of one gate would run as an unfused kernel in the single-state
+        // path; here every pass is a tile pass, so give singletons their stages
+        BCirc bc{};
+        bc.tiles = int32_t(uint64_t(1) << (ne - K));
+        bc.npasses = int32_t(plans[size_t(c)].size());
+        if (bc.npasses == 0) {
+            // no gates: still one (empty) pass to produce the observable
+            Pass ps;
+            ps.k = K;
+            for (int b = 0; b < K; ++b) ps.pos[b] = b;
+            plans[size_t(c)].push_back(ps);
+            bc.npasses = 1;
+        }
+        bc.term_beg = int32_t(B.tmask.size());
+        for (int64_t t = term_off[c]; t < term_off[c + 1]; ++t) {
+            if (n < 64 && (qmasks[t] >> n)) return "circuit " + std::to_string(c) + ": term names a qubit >= n";
+            uint64_t pm = 0;
+            for (int q = 0; q < n; ++q)
+                if ((qmasks[t] >> q) & 1) pm |= uint64_t(1) << pos_in(ne, q);
+            B.tmask.push_back(pm);
+            B.tw.push_back(w ? w[t] : 1.0);
+            mix(B.shape_key, qmasks[t]);
+        }
+        bc.term_end = int32_t(B.tmask.size());
+        if (bc.npasses > 1 || bc.tiles > 1) {
+            bc.state_off = B.state_amps;
+            B.state_amps += uint64_t(1) << ne;
+        }
+        bc.part_off = B.partial_count;
+        B.partial_count += uint64_t(bc.tiles);
+        B.circs.push_back(bc);
+        if (bc.npasses > maxp) maxp = bc.npasses;
+    }
+    // pass records
+    for (int c = 0; c < nb; ++c) {
+        std::vector<Pass>& pl = plans[size_t(c)];
+        for (size_t p = 0; p < pl.size(); ++p) {
+            Pass& ps = pl[p];
+            if (ps.single || ps.stages.empty()) {
+                // one-gate (or empty) pass: a single canonical stage holding it
+                ps.single = false;
+                ps.stages.clear();
+                Stage st;
+                st.nr = K - 8;
+                for (int j = 0; j < st.nr; ++j) st.rbits[j] = 8 + j;
+                // put the gate's bits into the register set if needed
+                uint64_t need = 0;
+                int loc[64];
+                for (int q = 0; q < 64; ++q) loc[q] = -1;
+                for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
+                for (int gi : ps.gates) {
+                    const PGate& x = lowered[size_t(c)][size_t(gi)];
+                    need |= uint64_t(1) << loc[x.p0];
+                    if (x.kind != QSV_G1Q) need |= uint64_t(1) << loc[x.p1];
+                }
+                if (need & 0xFF) {   // a low local bit: use a register set holding the gate's bits
+                    int j = 0;
+                    for (int b = 0; b < ps.k && j < st.nr; ++b)
+                        if ((need >> b) & 1) st.rbits[j++] = b;
+                    for (int b = ps.k - 1; b >= 0 && j < st.nr; --b)
+                        if (!((need >> b) & 1)) {
+                            need |= uint64_t(1) << b;
+                            st.rbits[j++] = b;
+                        }
+                    std::sort(st.rbits, st.rbits + st.nr);
+                    Stage s0, s2;   // canonical load stage and store stage around it
+                    s0.nr = s2.nr = st.nr;
+                    for (int j2 = 0; j2 < st.nr; ++j2) s0.rbits[j2] = s2.rbits[j2] = 8 + j2;
+                    st.gates = ps.gates;
+                    ps.stages.push_back(s0);
+                    ps.stages.push_back(st);
+                    ps.stages.push_back(s2);
+                } else {
+                    st.gates = ps.gates;
+                    ps.stages.push_back(st);
+                }
+            }
+            const size_t off = B.plan.size();
+            const size_t bytes = pass_record_bytes(dtype, ps);
+            B.plan.resize(off + bytes, 0);
+            if (!write_pass_record(dtype, B.plan.data() + off, lowered[size_t(c)], ps))
+                return "internal planner error";
+            BPass bp{};
+            bp.circ = c;
+            bp.level = int32_t(p);
+            bp.rec_off = uint32_t(off);
+            bp.flags = (p == 0 ? BP_FIRST : 0) | (p + 1 == pl.size() ? BP_LAST : 0);
+            B.passes.push_back(bp);
+        }
+    }
+    if (B.plan.size() >= (size_t(1) << 32)) return "batch plan too large";
+    // items, pass-level-major; within a level, larger circuits first
+    std::vector<int> pass_first(static_cast<size_t>(nb), 0);
+    {
+        int k = 0;
+        for (int c = 0; c < nb; ++c) {
+            pass_first[size_t(c)] = k;
+            k += B.circs[size_t(c)].npasses;
+        }
+    }
+    std::vector<int> order(static_cast<size_t>(nb));
+    for (int c = 0; c < nb; ++c) order[size_t(c)] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) {
+        return B.circs[size_t(a)].tiles > B.circs[size_t(b2)].tiles;
+    });
+    for (int lv = 0; lv < maxp; ++lv)
+        for (int c : order) {
+            const BCirc& bc = B.circs[size_t(c)];
+            if (lv >= bc.npasses) continue;
+            for (int t = 0; t < bc.tiles; ++t) B.items.push_back(BItem{pass_first[size_t(c)] + lv, t});
+        }
+    (void)amp;
+    return "";
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t plan, circs, passes, items, tmask, tw, total;
+};
+
+Layout upload_layout(const BatchBuild& B) {
+    Layout L{};
+    size_t o = 0;
+    L.plan = o; o = align256(o + B.plan.size());
+    L.circs = o; o = align256(o + B.circs.size() * sizeof(BCirc));
+    L.passes = o; o = align256(o + B.passes.size() * sizeof(BPass));
+    L.items = o; o = align256(o + B.items.size() * sizeof(BItem));
+    L.tmask = o; o = align256(o + (B.tmask.size() + 1) * sizeof(uint64_t));
+    L.tw = o; o = align256(o + (B.tw.size() + 1) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+template <typename R, int K>
+hipError_t launch_batch(qsv_ctx ctx, hipStream_t stream, const char* dev, const Layout& L,
+                        int nb, int nitems, void* states, unsigned* ctr, double* partials,
+                        double* out) {
+    using V = typename V2T<R>::type;
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nbk = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbk, k_batch<R, K>, kThreads, 0) !=
+                hipSuccess || nbk < 1)
+            nbk = 1;
+        per_cu = nbk;
+    }
+    unsigned grid = unsigned(per_cu) * unsigned(ctx->num_cus);
+    if (grid > unsigned(nitems)) grid = unsigned(nitems);
+    if (grid == 0) grid = 1;
+    const unsigned spin_limit = 1u << 22;   // x s_sleep(8): about 2 s before giving up
+    hipLaunchKernelGGL((k_batch<R, K>), dim3(grid), dim3(kThreads), 0, stream,
+                       static_cast<V*>(states), dev + L.plan,
+                       reinterpret_cast<const BCirc*>(dev + L.circs),
+                       reinterpret_cast<const BPass*>(dev + L.passes),
+                       reinterpret_cast<const BItem*>(dev + L.items), nitems,
+                       reinterpret_cast<const uint64_t*>(dev + L.tmask),
+                       reinterpret_cast<const double*>(dev + L.tw), ctr, partials, out, spin_limit);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch_k(qsv_ctx ctx, hipStream_t stream, int K, const char* dev, const Layout& L,
+                          int nb, int nitems, void* states, unsigned* ctr, double* partials,
+                          double* out) {
+    switch (K) {
+    case 10: return launch_batch<R, 10>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
+    case 11: return launch_batch<R, 11>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
+    case 12: return launch_batch<R, 12>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- driver
+struct BatchRun {
+    Layout L;
+    size_t ctr_words = 0, partial_count = 0, state_bytes = 0;
+    int nitems = 0;
+};
+
+// Enqueue one batch (upload, counter reset, kernel, result download) on
+// `stream`, using the context's batch buffers (grown on demand beforehand).
+static hipError_t enqueue_batch(qsv_ctx ctx, hipStream_t stream, int dtype, int K, int nb,
+                                const BatchRun& R) {
+    char* dev = static_cast<char*>(ctx->d_batch);
+    hipError_t e = hipMemcpyAsync(dev, ctx->h_batch, R.L.total, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    unsigned* ctr = reinterpret_cast<unsigned*>(dev + ctx->batch_ctr_off);
+    double* out = reinterpret_cast<double*>(dev + ctx->batch_out_off);
+    double* partials = reinterpret_cast<double*>(dev + ctx->batch_part_off);
+    void* states = dev + ctx->batch_state_off;
+    const size_t zw = R.ctr_words;   // item counter, error flag, per-circuit completion counts
+    hipLaunchKernelGGL(k_zero, dim3(unsigned((zw + 255) / 256)), dim3(256), 0, stream, ctr, zw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_before_on(ctx, stream, dtype == QSV_C128 ? "batch_c128" : "batch_c64", 0.0);
+    e = dtype == QSV_C128
+            ? launch_batch_k<double>(ctx, stream, K, dev, R.L, nb, R.nitems, states, ctr, partials, out)
+            : launch_batch_k<float>(ctx, stream, K, dev, R.L, nb, R.nitems, states, ctr, partials, out);
+    prof_after_on(ctx, stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(ctx->h_batch_out, out, sizeof(double) * (size_t(nb) + 1),
+                          hipMemcpyDeviceToHost, stream);
+}
+
+// Plan and stage a batch for tile shape (K, L); sizes the context buffers.
+static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off,
+                              const qsv_gate* g, const double* params, int64_t nparams,
+                              const int64_t* term_off, const uint64_t* qmasks, const double* w,
+                              int dtype, int K, int L, BatchRun& R, uint64_t& key) {
+    BatchBuild B;
+    std::string err = build_batch(nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
+                                  K, L, B);
+    if (!err.empty()) {
+        ctx->last_error = "qsv_batch_run: " + err;
+        return QSV_ERR_ARG;
+    }
+    key = B.shape_key;
+    R.L = upload_layout(B);
+    R.nitems = int(B.items.size());
+    R.ctr_words = size_t(kCtrDone) + size_t(nb);
+    R.partial_count = B.partial_count;
+    R.state_bytes = B.state_amps * amp_bytes(dtype);
+    // device buffer: [upload | counters | out | partials | states]
+    const size_t ctr_off = R.L.total;
+    const size_t out_off = align256(ctr_off + R.ctr_words * sizeof(unsigned));
+    const size_t part_off = align256(out_off + (size_t(nb) + 1) * sizeof(double));
+    const size_t state_off = align256(part_off + (R.partial_count + 1) * sizeof(double));
+    const size_t need = state_off + R.state_bytes + 256;
+    if (need > ctx->batch_bytes || R.L.total > ctx->h_batch_bytes ||
+        size_t(nb) + 1 > ctx->h_batch_out_n) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess && ctx->batch_stream) e = hipStreamSynchronize(ctx->batch_stream);
+        if (e != hipSuccess) {
+            ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
+            return QSV_ERR_HIP;
+        }
+        if (ctx->batch_graph_exec) {
+            hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
+            ctx->batch_graph_exec = nullptr;
+            ctx->batch_graph_key = 0;
+        }
+        if (need > ctx->batch_bytes) {
+            if (ctx->d_batch) hipFree(ctx->d_batch);
+            ctx->d_batch = nullptr;
+            ctx->batch_bytes = 0;
+            if (hipMalloc(&ctx->d_batch, need) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->last_error = "qsv_batch_run: device allocation of " + std::to_string(need) + " bytes failed";
+                return QSV_ERR_NOMEM;
+            }
+            ctx->batch_bytes = need;
+        }
+        if (R.L.total > ctx->h_batch_bytes) {
+            if (ctx->h_batch) hipHostFree(ctx->h_batch);
+            ctx->h_batch = nullptr;
+            ctx->h_batch_bytes = 0;
+            if (hipHostMalloc(&ctx->h_batch, R.L.total, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->last_error = "qsv_batch_run: pinned allocation failed";
+                return QSV_ERR_NOMEM;
+            }
+            ctx->h_batch_bytes = R.L.total;
+        }
+        if (size_t(nb) + 1 > ctx->h_batch_out_n) {
+            if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
+            ctx->h_batch_out = nullptr;
+            ctx->h_batch_out_n = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_batch_out), sizeof(double) * (size_t(nb) + 1),
+                              hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->last_error = "qsv_batch_run: pinned allocation failed";
+                return QSV_ERR_NOMEM;
+            }
+            ctx->h_batch_out_n = size_t(nb) + 1;
+        }
+    }
+    ctx->batch_ctr_off = ctr_off;
+    ctx->batch_out_off = out_off;
+    ctx->batch_part_off = part_off;
+    ctx->batch_state_off = state_off;
+    char* h = static_cast<char*>(ctx->h_batch);
+    std::memcpy(h + R.L.plan, B.plan.data(), B.plan.size());
+    std::memcpy(h + R.L.circs, B.circs.data(), B.circs.size() * sizeof(BCirc));
+    std::memcpy(h + R.L.passes, B.passes.data(), B.passes.size() * sizeof(BPass));
+    std::memcpy(h + R.L.items, B.items.data(), B.items.size() * sizeof(BItem));
+    if (!B.tmask.empty()) std::memcpy(h + R.L.tmask, B.tmask.data(), B.tmask.size() * sizeof(uint64_t));
+    if (!B.tw.empty()) std::memcpy(h + R.L.tw, B.tw.data(), B.tw.size() * sizeof(double));
+    return QSV_OK;
+}
+
+static qsv_status finish_batch(qsv_ctx ctx, hipStream_t stream, int nb, double* out) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorName(e) + " " + hipGetErrorString(e);
+        return QSV_ERR_HIP;
+    }
+    unsigned flag = 0;
+    e = hipMemcpy(&flag, static_cast<char*>(ctx->d_batch) + ctx->batch_ctr_off + sizeof(unsigned),
+                  sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess || flag) {
+        ctx->last_error = "qsv_batch_run: a dependency wait exceeded its spin limit";
+        return QSV_ERR_HIP;
+    }
+    std::memcpy(out, ctx->h_batch_out, sizeof(double) * size_t(nb));
+    return QSV_OK;
+}
+
+// Tile shapes the autotuner tries for a batch, best first by default.
+static const int kTuneShapes[][2] = {{12, 3}, {11, 3}, {10, 2}, {12, 4}, {11, 2}, {10, 3}};
+
+}  // namespace qsv
+
+using namespace qsv;
 
 extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off,
                                     const qsv_gate* g, const double* params, int64_t nparams,
                                     const int64_t* term_off, const uint64_t* qmasks,
                                     const double* w, int dtype, double* out, int flags) {
-    (void)nb; (void)nq; (void)gate_off; (void)g; (void)params; (void)nparams; (void)term_off;
-    (void)qmasks; (void)w; (void)dtype; (void)out; (void)flags;
     if (!ctx) return QSV_ERR_ARG;
-    ctx->last_error = "qsv_batch_run: not available in this build";
-    return QSV_ERR_ARG;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+        ctx->last_error = "the context's device is not the current HIP device";
+        return QSV_ERR_ARG;
+    }
+    if (dtype != QSV_C64 && dtype != QSV_C128) {
+        ctx->last_error = "qsv_batch_run: dtype must be QSV_C64 or QSV_C128";
+        return QSV_ERR_DTYPE;
+    }
+    if (nb < 1 || !nq || !gate_off || !term_off || !out || (nparams > 0 && !params) || nparams < 0) {
+        ctx->last_error = "qsv_batch_run: bad arguments";
+        return QSV_ERR_ARG;
+    }
+    if (flags & ~(QSV_FLAG_CAPTURE_GRAPH | QSV_FLAG_TUNE)) {
+        ctx->last_error = "qsv_batch_run: unknown flag";
+        return QSV_ERR_ARG;
+    }
+    for (int c = 0; c < nb; ++c) {
+        if (nq[c] < 1 || nq[c] > kMaxBatchQubits) {
+            ctx->last_error = "qsv_batch_run: circuit " + std::to_string(c) + " has " +
+                              std::to_string(nq[c]) + " qubits (allowed 1.." +
+                              std::to_string(kMaxBatchQubits) + ")";
+            return QSV_ERR_SIZE;
+        }
+        if (gate_off[c + 1] < gate_off[c] || term_off[c + 1] < term_off[c]) {
+            ctx->last_error = "qsv_batch_run: offsets must be non-decreasing";
+            return QSV_ERR_ARG;
+        }
+    }
+    if (gate_off[0] != 0 || term_off[0] != 0 || (gate_off[nb] > 0 && !g) || (term_off[nb] > 0 && !qmasks)) {
+        ctx->last_error = "qsv_batch_run: bad offsets or arrays";
+        return QSV_ERR_ARG;
+    }
+    // tile shape: the tuned choice for this batch shape, if any
+    BatchRun R;
+    uint64_t key = 0;
+    int K = 12, L = dtype == QSV_C128 ? 3 : 4;
+    {
+        // shape key without the tile shape, to look up a tuned choice
+        BatchRun R0;
+        qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
+                                   dtype, K, L, R0, key);
+        if (s != QSV_OK) return s;
+        int tk = 0, tl = 0;
+        if (tune_lookup(ctx, key, dtype, &tk, &tl)) {
+            K = tk;
+            L = tl;
+        } else if (flags & QSV_FLAG_TUNE) {
+            // time each candidate once (every run computes the full, correct batch)
+            double best = 1e30;
+            for (const auto& sh : kTuneShapes) {
+                uint64_t k2 = 0;
+                BatchRun Rc;
+                s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
+                                sh[0], sh[1], Rc, k2);
+                if (s != QSV_OK) return s;
+                hipEvent_t e0, e1;
+                hipEventCreate(&e0);
+                hipEventCreate(&e1);
+                hipEventRecord(e0, ctx->stream);
+                hipError_t e = enqueue_batch(ctx, ctx->stream, dtype, sh[0], nb, Rc);
+                hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) s = finish_batch(ctx, ctx->stream, nb, out);
+                float ms = 0.f;
+                if (e == hipSuccess && s == QSV_OK) hipEventElapsedTime(&ms, e0, e1);
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                if (e != hipSuccess) {
+                    ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
+                    return QSV_ERR_HIP;
+                }
+                if (s != QSV_OK) return s;
+                if (ms < best) {
+                    best = ms;
+                    K = sh[0];
+                    L = sh[1];
+                }
+            }
+            tune_store(ctx, key, dtype, K, L, best);
+        }
+    }
+    qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
+                               dtype, K, L, R, key);
+    if (s != QSV_OK) return s;
+    hipError_t e;
+    if (flags & QSV_FLAG_CAPTURE_GRAPH) {
+        if (!ctx->batch_stream) {
+            if (hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking) != hipSuccess) {
+                ctx->last_error = "qsv_batch_run: stream creation failed";
+                return QSV_ERR_HIP;
+            }
+        }
+        const uint64_t gkey = key ^ (uint64_t(K) << 56) ^ (uint64_t(L) << 48) ^ uint64_t(R.L.total);
+        // order the batch after the context stream's earlier work
+        e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess && (!ctx->batch_graph_exec || ctx->batch_graph_key != gkey)) {
+            if (ctx->batch_graph_exec) {
+                hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
+                ctx->batch_graph_exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(ctx->batch_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const bool prof = ctx->profiling;
+                ctx->profiling = false;   // no event records inside the graph
+                hipError_t e2 = enqueue_batch(ctx, ctx->batch_stream, dtype, K, nb, R);
+                ctx->profiling = prof;
+                e = hipStreamEndCapture(ctx->batch_stream, &graph);
+                if (e2 != hipSuccess) e = e2;
+            }
+            hipGraphExec_t exec = nullptr;
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) hipGraphDestroy(graph);
+            if (e == hipSuccess) {
+                ctx->batch_graph_exec = exec;
+                ctx->batch_graph_key = gkey;
+            }
+        }
+        if (e == hipSuccess) {
+            prof_before_on(ctx, ctx->batch_stream, dtype == QSV_C128 ? "batch_graph_c128" : "batch_graph_c64", 0.0);
+            e = hipGraphLaunch(static_cast<hipGraphExec_t>(ctx->batch_graph_exec), ctx->batch_stream);
+            prof_after_on(ctx, ctx->batch_stream);
+        }
+        if (e != hipSuccess) {
+            ctx->last_error = std::string("qsv_batch_run (graph): ") + hipGetErrorString(e);
+            return QSV_ERR_HIP;
+        }
+        return finish_batch(ctx, ctx->batch_stream, nb, out);
+    }
+    e = enqueue_batch(ctx, ctx->stream, dtype, K, nb, R);
+    if (e != hipSuccess) {
+        ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
+        return QSV_ERR_HIP;
+    }
+    return finish_batch(ctx, ctx->stream, nb, out);
 }

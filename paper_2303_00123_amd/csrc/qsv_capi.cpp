@@ -45,6 +45,9 @@ qsv_status check_state(qsv_state st) {
 
 inline int pos_of(int n, int q) { return n - 1 - q; }
 
+}  // namespace
+
+namespace qsv {
 // 2x2 rotation exp(-i theta P / 2) = cos(theta/2) I - i sin(theta/2) P
 void rotation_matrix(int axis, double theta, double* m) {
     const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
@@ -61,6 +64,9 @@ void rotation_matrix(int axis, double theta, double* m) {
         break;
     }
 }
+}  // namespace qsv
+
+namespace {
 
 // Validate and lower gates to index-bit positions; rotations become G1Q.
 qsv_status lower(qsv_ctx ctx, int n, const qsv_gate* g, int64_t ng, const double* params,
@@ -192,16 +198,22 @@ static hipEvent_t pool_event(qsv_ctx ctx) {
 }
 
 void prof_before(qsv_ctx ctx, const char* name, double bytes) {
+    prof_before_on(ctx, ctx->stream, name, bytes);
+}
+
+void prof_after(qsv_ctx ctx) { prof_after_on(ctx, ctx->stream); }
+
+void prof_before_on(qsv_ctx ctx, hipStream_t stream, const char* name, double bytes) {
     if (!ctx->profiling) return;
     ProfRec r{name, bytes, pool_event(ctx), pool_event(ctx)};
     if (!r.start || !r.stop) return;
-    hipEventRecord(r.start, ctx->stream);
+    hipEventRecord(r.start, stream);
     ctx->prof.push_back(r);
 }
 
-void prof_after(qsv_ctx ctx) {
+void prof_after_on(qsv_ctx ctx, hipStream_t stream) {
     if (!ctx->profiling || ctx->prof.empty()) return;
-    hipEventRecord(ctx->prof.back().stop, ctx->stream);
+    hipEventRecord(ctx->prof.back().stop, stream);
 }
 
 }  // namespace qsv
@@ -271,8 +283,12 @@ qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
     if (ctx->h_plan) hipHostFree(ctx->h_plan);
     if (ctx->plan_copied) hipEventDestroy(ctx->plan_copied);
     for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
+    if (ctx->batch_stream) hipStreamSynchronize(ctx->batch_stream);
     if (ctx->batch_graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
     if (ctx->d_batch) hipFree(ctx->d_batch);
+    if (ctx->h_batch) hipHostFree(ctx->h_batch);
+    if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
+    if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
     delete ctx;
     return QSV_OK;
 }

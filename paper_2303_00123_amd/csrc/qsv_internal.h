@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "qsv.h"
@@ -147,11 +149,21 @@ struct qsv_ctx_s {
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
 
-    // batch scratch
+    // batch: device buffer [upload | counters | out | partials | states], pinned staging
     void* d_batch = nullptr;
     size_t batch_bytes = 0;
-    void* batch_graph_exec = nullptr;   // hipGraphExec_t
+    void* h_batch = nullptr;
+    size_t h_batch_bytes = 0;
+    double* h_batch_out = nullptr;
+    size_t h_batch_out_n = 0;
+    size_t batch_ctr_off = 0, batch_out_off = 0, batch_part_off = 0, batch_state_off = 0;
+    hipStream_t batch_stream = nullptr;   // capture stream (default priority)
+    void* batch_graph_exec = nullptr;     // hipGraphExec_t
     uint64_t batch_graph_key = 0;
+
+    // autotuner choices: batch shape key -> (tile_bits, low_bits)
+    std::map<uint64_t, std::pair<int, int>> tuned;
+    bool tune_loaded = false;
 };
 
 struct qsv_state_s {
@@ -173,9 +185,21 @@ hipError_t plan_staging(qsv_ctx ctx, size_t bytes, void** host);
 hipError_t plan_upload(qsv_ctx ctx, size_t bytes, void** dev);
 hipError_t ensure_aux(qsv_ctx ctx, size_t doubles);
 
-// profiling helpers: bracket a launch
+// profiling helpers: bracket a launch (on the context stream, or on `stream`)
 void prof_before(qsv_ctx ctx, const char* name, double bytes);
 void prof_after(qsv_ctx ctx);
+void prof_before_on(qsv_ctx ctx, hipStream_t stream, const char* name, double bytes);
+void prof_after_on(qsv_ctx ctx, hipStream_t stream);
+
+// exp(-i theta P / 2) for Pauli `axis`, as a 2x2 row-major (re, im) matrix
+void rotation_matrix(int axis, double theta, double* m);
+
+constexpr int kMaxBatchQubits = 24;
+
+// Autotuner cache (qsv_tune.cpp): tuned tile shape for a batch shape key,
+// kept per context and, if QSV_TUNE_CACHE names a file, across processes.
+bool tune_lookup(qsv_ctx ctx, uint64_t key, int dtype, int* tile_bits, int* low_bits);
+void tune_store(qsv_ctx ctx, uint64_t key, int dtype, int tile_bits, int low_bits, double ms);
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on ctx->stream and return the launch status.
@@ -188,6 +212,11 @@ hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g);
 
 // Largest tile (log2 amplitudes) the tile kernel supports for a dtype.
 int tile_bits_max(int dtype);
+
+// Device record of one tile pass (header, stages, fused gates): its size
+// bound and its contents (false on a planner inconsistency).
+size_t pass_record_bytes(int dtype, const Pass& ps);
+bool write_pass_record(int dtype, char* dst, const std::vector<PGate>& gates, const Pass& ps);
 
 // Tile passes: uploads the plan for all passes, then launches them in order.
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,

@@ -16,172 +16,12 @@
 //
 // LDS holds the tile with an XOR swizzle on the 16-byte (c128) or 8-byte
 // (c64) slot index, so strided stage mappings spread over the banks.
-#include <type_traits>
-
-#include "qsv_common.h"
-#include "qsv_internal.h"
+#include "qsv_tile_core.h"
 
 namespace qsv {
 namespace {
 
-constexpr int kThreads = kTileThreads;
-
-template <typename R>
-struct TileK;
-template <>
-struct TileK<double> { static constexpr int value = 12; };   // 4096 x 16 B = 64 KiB
-template <>
-struct TileK<float> { static constexpr int value = 13; };    // 8192 x 8 B = 64 KiB
-
-template <typename R>
-__device__ __forceinline__ uint32_t swz(uint32_t e) {
-    return tile_swz(e, int(sizeof(typename V2T<R>::type)));
-}
-
-// Deposit the low `k` bits of e at the positions pos[0..k).
-__device__ __forceinline__ uint64_t deposit(uint32_t e, const int32_t* pos, int k) {
-    uint64_t off = 0;
-    for (int i = 0; i < k; ++i)
-        if ((e >> i) & 1u) off |= uint64_t(1) << pos[i];
-    return off;
-}
-__device__ __forceinline__ uint32_t deposit32(uint32_t e, const int32_t* pos, int k) {
-    uint32_t off = 0;
-    for (int i = 0; i < k; ++i)
-        if ((e >> i) & 1u) off |= 1u << pos[i];
-    return off;
-}
-
-template <int B>
-using IC = std::integral_constant<int, B>;
-
-// ---------------------------------------------------- register gate bodies
-template <int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_1q(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (!(i & (1 << B))) {
-            const V a = v[i], b = v[i | (1 << B)];
-            mv2(m, a, b, v[i], v[i | (1 << B)]);
-        }
-}
-
-template <typename R, typename V>
-__device__ __forceinline__ V cmul(const V& a, R dr, R di) {
-    V o;
-    o.x = a.x * dr - a.y * di;
-    o.y = a.x * di + a.y * dr;
-    return o;
-}
-
-template <int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_1d(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        if (i & (1 << B)) v[i] = cmul(v[i], m[2], m[3]);
-        else v[i] = cmul(v[i], m[0], m[1]);
-    }
-}
-
-template <int C, int T, int CS, typename R, typename V, int P>
-__device__ __forceinline__ void rg_c1q(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
-            const V a = v[i], b = v[i | (1 << T)];
-            mv2(m, a, b, v[i], v[i | (1 << T)]);
-        }
-}
-
-template <int C, int T, int CS, typename V, int P>
-__device__ __forceinline__ void rg_cx(V (&v)[P]) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
-            const V a = v[i];
-            v[i] = v[i | (1 << T)];
-            v[i | (1 << T)] = a;
-        }
-}
-
-template <int C, int T, int CS, typename R, typename V, int P>
-__device__ __forceinline__ void rg_cd(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS) {
-            if (i & (1 << T)) v[i] = cmul(v[i], m[2], m[3]);
-            else v[i] = cmul(v[i], m[0], m[1]);
-        }
-}
-
-template <int A, int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_2q(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (!(i & (1 << A)) && !(i & (1 << B))) {
-            V in[4], out[4];
-            in[0] = v[i];
-            in[1] = v[i | (1 << B)];
-            in[2] = v[i | (1 << A)];
-            in[3] = v[i | (1 << A) | (1 << B)];
-            mv4(m, in, out);
-            v[i] = out[0];
-            v[i | (1 << B)] = out[1];
-            v[i | (1 << A)] = out[2];
-            v[i | (1 << A) | (1 << B)] = out[3];
-        }
-}
-
-// ------------------------------------------------------ runtime dispatch
-template <int RB, typename F>
-__device__ __forceinline__ void on_bit(int b, F&& f) {
-    switch (b) {
-    case 0: f(IC<0>{}); break;
-    case 1: f(IC<1>{}); break;
-    case 2: if constexpr (RB > 2) f(IC<2>{}); break;
-    case 3: if constexpr (RB > 3) f(IC<3>{}); break;
-    case 4: if constexpr (RB > 4) f(IC<4>{}); break;
-    default: if constexpr (RB > 5) f(IC<5>{}); break;
-    }
-}
-
-// Controlled kinds are emitted for control state 1 only (the host lowers a
-// control-state-0 gate to a 2-qubit gate), and 2-qubit gates with r0 < r1
-// (the host permutes the matrix), which keeps the number of compiled
-// specialisations -- and the kernel's instruction footprint -- small.
-template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_gate(V (&v)[P], const TGate<R>& g) {
-    const int kind = g.kind;
-    if (kind == DK_1Q) {
-        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1q<decltype(B)::value>(v, g.m); });
-    } else if (kind == DK_1D) {
-        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1d<decltype(B)::value>(v, g.m); });
-    } else if (kind == DK_2Q) {
-        on_bit<RB>(g.r0, [&](auto A) __attribute__((always_inline)) {
-            on_bit<RB>(g.r1, [&](auto B) __attribute__((always_inline)) {
-                if constexpr (decltype(A)::value < decltype(B)::value)
-                    rg_2q<decltype(A)::value, decltype(B)::value>(v, g.m);
-            });
-        });
-    } else {
-        on_bit<RB>(g.r0, [&](auto C) __attribute__((always_inline)) {
-            on_bit<RB>(g.r1, [&](auto T) __attribute__((always_inline)) {
-                constexpr int c = decltype(C)::value, t = decltype(T)::value;
-                if constexpr (c != t) {
-                    if (kind == DK_CX) rg_cx<c, t, 1>(v);
-                    else if (kind == DK_CD) rg_cd<c, t, 1>(v, g.m);
-                    else rg_c1q<c, t, 1>(v, g.m);
-                }
-            });
-        });
-    }
-}
-
-template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restrict__ gates, int gb,
-                                            int ge) {
-    for (int g = gb; g < ge; ++g) apply_gate<RB>(v, gates[g]);
-}
+using namespace tile;
 
 // ------------------------------------------------------------ the kernel
 // One workgroup per tile.  Every stage record (including the first and the
@@ -216,21 +56,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
 #pragma unroll
     for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
 
-    for (int st = 0; st < nst; ++st) {
-        const TStage& S = stg[st];
-        // LDS byte address of slot u = swz(eb | du) * ES = swz(eb) * ES ^ su[u]
-        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
-        if (st > 0) {
-#pragma unroll
-            for (int u = 0; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sb ^ S.su[u]));
-        }
-        apply_range<RB>(v, gates, S.gbeg, S.gend);
-        if (st < nst - 1) {
-#pragma unroll
-            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su[u])) = v[u];
-            __syncthreads();
-        }
-    }
+    run_stages<R, K>(v, lds, stg, nst, gates, tid);
 #pragma unroll
     for (int u = 0; u < P; ++u) sp[hdr->du[u]] = v[u];
 }
@@ -330,11 +156,66 @@ hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, const char* dplan) 
     }
 }
 
+// Bytes of a pass's device record (header, stages, gates; 256-byte
+// aligned).  Fusion never adds gates, so the unfused count bounds the size.
+template <typename R>
+size_t record_bytes_t(const Pass& ps) {
+    size_t b = sizeof(TPassHdr) + ps.stages.size() * sizeof(TStage) + ps.gates.size() * sizeof(TGate<R>);
+    return (b + 255) & ~size_t(255);
+}
+
+// Fill the device record of a tile pass at h.  False on a planner bug.
+template <typename R>
+bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
+    using V = typename V2T<R>::type;
+    TPassHdr* hd = reinterpret_cast<TPassHdr*>(h);
+    hd->k = ps.k;
+    hd->nstages = int32_t(ps.stages.size());
+    hd->pad = 0;
+    int loc[64];
+    for (int p = 0; p < 64; ++p) loc[p] = -1;
+    for (int b = 0; b < 24; ++b) hd->pos[b] = b < ps.k ? ps.pos[b] : 0;
+    for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
+    const int rb = ps.k - 8;
+    for (int u = 0; u < 32; ++u) {
+        uint64_t off = 0;
+        if (u < (1 << rb))
+            for (int j = 0; j < rb; ++j)
+                if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[8 + j];
+        hd->du[u] = off;
+    }
+    TStage* ts = reinterpret_cast<TStage*>(h + sizeof(TPassHdr));
+    TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + sizeof(TPassHdr) + ps.stages.size() * sizeof(TStage));
+    int gi = 0;
+    for (size_t si = 0; si < ps.stages.size(); ++si) {
+        const Stage& st = ps.stages[si];
+        ts[si].gbeg = gi;
+        uint32_t used = 0;
+        for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
+        int tj = 0;
+        for (int b = 0; b < ps.k && tj < 8; ++b)
+            if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
+        for (; tj < 8; ++tj) ts[si].tbits[tj] = 0;
+        for (int u = 0; u < 32; ++u) {
+            uint32_t e = 0;
+            if (u < (1 << st.nr))
+                for (int j = 0; j < st.nr; ++j)
+                    if ((u >> j) & 1) e |= 1u << st.rbits[j];
+            ts[si].su[u] = tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
+        }
+        for (const PGate& fg : fuse_stage(gates, st.gates))
+            if (!to_device_gate<R>(fg, loc, st, tg[gi++])) return false;
+        ts[si].gend = gi;
+    }
+    hd->ngates = gi;
+    return true;
+}
+
 template <typename R>
 hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& gates,
                         const std::vector<Pass>& passes) {
     using V = typename V2T<R>::type;
-    // upload layout: per tile pass, header, stages, gates (256-byte aligned)
+    // upload layout: one record per tile pass
     size_t bytes = 0;
     std::vector<size_t> offs(passes.size(), 0);
     for (size_t i = 0; i < passes.size(); ++i) {
@@ -342,9 +223,7 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         if (passes[i].k < kMinTileBits || passes[i].k > TileK<R>::value || n - passes[i].k > 30)
             return hipErrorInvalidValue;
         offs[i] = bytes;
-        bytes += sizeof(TPassHdr) + passes[i].stages.size() * sizeof(TStage) +
-                 passes[i].gates.size() * sizeof(TGate<R>);
-        bytes = (bytes + 255) & ~size_t(255);
+        bytes += record_bytes_t<R>(passes[i]);
     }
     char* dev = nullptr;
     if (bytes) {
@@ -352,51 +231,9 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         hipError_t e = plan_staging(ctx, bytes, &host);
         if (e != hipSuccess) return e;
         char* h = static_cast<char*>(host);
-        for (size_t i = 0; i < passes.size(); ++i) {
-            const Pass& ps = passes[i];
-            if (ps.single) continue;
-            TPassHdr* hd = reinterpret_cast<TPassHdr*>(h + offs[i]);
-            hd->k = ps.k;
-            hd->nstages = int32_t(ps.stages.size());
-            hd->ngates = int32_t(ps.gates.size());
-            hd->pad = 0;
-            int loc[64];
-            for (int p = 0; p < 64; ++p) loc[p] = -1;
-            for (int b = 0; b < 24; ++b) hd->pos[b] = b < ps.k ? ps.pos[b] : 0;
-            for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
-            const int rb = ps.k - 8;
-            for (int u = 0; u < 32; ++u) {
-                uint64_t off = 0;
-                if (u < (1 << rb))
-                    for (int j = 0; j < rb; ++j)
-                        if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[8 + j];
-                hd->du[u] = off;
-            }
-            TStage* ts = reinterpret_cast<TStage*>(h + offs[i] + sizeof(TPassHdr));
-            TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + offs[i] + sizeof(TPassHdr) +
-                                                       ps.stages.size() * sizeof(TStage));
-            int gi = 0;
-            for (size_t si = 0; si < ps.stages.size(); ++si) {
-                const Stage& st = ps.stages[si];
-                ts[si].gbeg = gi;
-                uint32_t used = 0;
-                for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
-                int tj = 0;
-                for (int b = 0; b < ps.k && tj < 8; ++b)
-                    if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
-                for (; tj < 8; ++tj) ts[si].tbits[tj] = 0;
-                for (int u = 0; u < 32; ++u) {
-                    uint32_t e = 0;
-                    if (u < (1 << st.nr))
-                        for (int j = 0; j < st.nr; ++j)
-                            if ((u >> j) & 1) e |= 1u << st.rbits[j];
-                    ts[si].su[u] = tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
-                }
-                for (const PGate& fg : fuse_stage(gates, st.gates))
-                    if (!to_device_gate<R>(fg, loc, st, tg[gi++])) return hipErrorInvalidValue;
-                ts[si].gend = gi;
-            }
-        }
+        for (size_t i = 0; i < passes.size(); ++i)
+            if (!passes[i].single && !write_record_t<R>(h + offs[i], gates, passes[i]))
+                return hipErrorInvalidValue;
         void* d = nullptr;
         e = plan_upload(ctx, bytes, &d);
         if (e != hipSuccess) return e;
@@ -420,6 +257,15 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
 }
 
 }  // namespace
+
+size_t pass_record_bytes(int dtype, const Pass& ps) {
+    return dtype == QSV_C128 ? record_bytes_t<double>(ps) : record_bytes_t<float>(ps);
+}
+
+bool write_pass_record(int dtype, char* dst, const std::vector<PGate>& gates, const Pass& ps) {
+    return dtype == QSV_C128 ? write_record_t<double>(dst, gates, ps)
+                             : write_record_t<float>(dst, gates, ps);
+}
 
 int tile_bits_max(int dtype) { return dtype == QSV_C128 ? TileK<double>::value : TileK<float>::value; }
 

@@ -1,0 +1,117 @@
+"""Batched persistent launch (qsv_batch_run) against the FP64 oracle and the
+single-state path: every circuit's <O> must match, eager, tuned and
+graph-replayed (with new angles between replays)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2303_00123_amd as qq
+    return qq
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context()
+    yield c
+    c.close()
+
+
+def mixed_batch(seed):
+    """Circuits of many widths: below the tile (padded), exactly one tile,
+    and several tiles with several passes; fixed gates and rotations."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate([1, 2, 3, 7, 10, 12, 13, 14, 15, 16, 11, 9]):
+        if n == 1:
+            c = W.Circuit(1, [W.g1(0, W.haar_unitary(2, rng)), W.grot(0, "Y", 0)],
+                          np.array([rng.uniform(0, 6.28)]), [((0,), 0.7)])
+        elif k % 2:
+            c = W.random_mix(n, 60, seed=seed * 100 + k)
+            c.observable = [((q,), float(rng.standard_normal())) for q in range(n)]
+        else:
+            c = W.ry_rz_cnot_ladder(n, 3, rng)
+        out.append(c)
+    return out
+
+
+def oracle_values(circs):
+    return np.array([O.expect_obs(O.run(c), c.observable) for c in circs])
+
+
+def tol(c, dtype):
+    wsum = max(1.0, sum(abs(w) for _, w in c.observable))
+    return (1e-12 if dtype == 2 else 2e-5) * wsum
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_batch_matches_oracle(q, ctx, dtype):
+    circs = mixed_batch(1)
+    got = ctx.batch_run(circs, dtype)
+    ref = oracle_values(circs)
+    for b, c in enumerate(circs):
+        assert abs(got[b] - ref[b]) <= tol(c, dtype), (b, c.n, got[b], ref[b])
+
+
+def test_batch_graph_replays_with_new_angles(q, ctx):
+    circs = mixed_batch(2)
+    rng = np.random.default_rng(7)
+    for rep in range(3):
+        for c in circs:
+            if c.params.size:
+                c.params = rng.uniform(0, 2 * np.pi, size=c.params.size)
+        got = ctx.batch_run(circs, q.QSV_C128, flags=q.FLAG_CAPTURE_GRAPH)
+        ref = oracle_values(circs)
+        for b, c in enumerate(circs):
+            assert abs(got[b] - ref[b]) <= tol(c, 2), (rep, b)
+        # eager work and synchronisation between replays
+        eager = ctx.batch_run(circs, q.QSV_C128)
+        assert np.max(np.abs(eager - got)) <= 1e-12
+
+
+def test_batch_tuned_shape_is_correct_and_cached(q, ctx):
+    circs = mixed_batch(3)
+    ref = oracle_values(circs)
+    for _ in range(2):
+        got = ctx.batch_run(circs, q.QSV_C128, flags=q.FLAG_TUNE)
+        for b, c in enumerate(circs):
+            assert abs(got[b] - ref[b]) <= tol(c, 2)
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_config4_batch_vs_single_state_path(q, ctx, dtype):
+    """256 circuits, 12..20 qubits, 6 layers RY RZ + CNOT ladder: each batch
+    result against the same circuit run alone through qsv_apply_circuit."""
+    circs = W.config4()
+    got = ctx.batch_run(circs, dtype)
+    for b, c in enumerate(circs):
+        st = q.State(ctx, c.n, dtype)
+        st.init_basis(0)
+        st.apply_circuit(c.gates, c.params)
+        ref = st.expect_z(c.observable)[1]
+        st.free()
+        assert abs(got[b] - ref) <= (1e-11 if dtype == 2 else 1e-5 * c.n), (b, c.n)
+    # and a few against the oracle
+    for b in (0, 1, 2):
+        c = circs[b]
+        if c.n <= 16:
+            assert abs(got[b] - O.expect_obs(O.run(c), c.observable)) <= (1e-11 if dtype == 2 else 1e-5 * c.n)
+
+
+def test_batch_rejects_bad_input(q, ctx):
+    c = W.random_mix(5, 10, seed=1)
+    bad = W.Circuit(5, [W.g1(7, W.H)], np.zeros(0), [((0,), 1.0)])
+    with pytest.raises(q.QsvError):
+        ctx.batch_run([c, bad], q.QSV_C128)
+    big = W.Circuit(25, [W.g1(0, W.H)], np.zeros(0), [((0,), 1.0)])
+    with pytest.raises(q.QsvError):
+        ctx.batch_run([big], q.QSV_C128)

@@ -2,14 +2,17 @@
 // gate engine: lambda = O psi, then for k = last..first
 //   rotation exp(-i theta P/2):  g_k = Im <lambda| P |psi>
 //   psi <- U_k^dag psi,  lambda <- U_k^dag lambda.
-// Each rotation's partial sum is fused into the pass that rewinds it, so a
-// rotation costs one read and one write of both vectors; per-block partials
-// are reduced in a fixed order on the device, and all gradients come back
-// to the host in one copy at the end.
+// Fused form (default): the reversed, daggered circuit is grouped into tile
+// passes over both vectors.  Inside a pass each rotation stays a separate
+// gate: its partial Im<lam|P|psi> over the tile is taken in registers right
+// before the rotation is rewound, reduced across each wave in a fixed
+// butterfly order and stored per (tile, wave, slot); a second kernel adds
+// them in a fixed order.  Every other gate may be fused as in the forward
+// passes.  Unfused form: one kernel per gate, each rotation's partial fused
+// into its rewind pass.  All gradients come back to the host in one copy.
 #include <cstring>
 
-#include "qsv_common.h"
-#include "qsv_internal.h"
+#include "qsv_tile_core.h"
 
 namespace qsv {
 namespace {
@@ -91,6 +94,148 @@ __global__ __launch_bounds__(kThreads) void k_sum_to(const double* __restrict__ 
     block_tree256<1>(red, out);
 }
 
+// ------------------------------------------------- two-vector tile passes
+using namespace tile;
+
+template <int B, int AXIS, typename V, int P>
+__device__ __forceinline__ double rot_part(const V (&v)[P], const V (&l)[P]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!(i & (1 << B))) {
+            const int j = i | (1 << B);
+            const double ar = v[i].x, ai = v[i].y, br = v[j].x, bi = v[j].y;
+            double qar, qai, qbr, qbi;   // (P psi)_i, (P psi)_j
+            if (AXIS == QSV_AXIS_X) {
+                qar = br; qai = bi; qbr = ar; qbi = ai;
+            } else if (AXIS == QSV_AXIS_Y) {
+                qar = bi; qai = -br; qbr = -ai; qbi = ar;
+            } else {
+                qar = ar; qai = ai; qbr = -br; qbi = -bi;
+            }
+            acc += double(l[i].x) * qai - double(l[i].y) * qar + double(l[j].x) * qbi -
+                   double(l[j].y) * qbr;
+        }
+    return acc;
+}
+
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_gate2(V (&v)[P], V (&l)[P], const TGate<R>& g,
+                                            double* __restrict__ part_out, uint32_t tid) {
+    if (g.kind == DK_ROT) {
+        double part = 0.0;
+        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) {
+            constexpr int b = decltype(B)::value;
+            if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(v, l);
+            else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(v, l);
+            else part = rot_part<b, QSV_AXIS_Z>(v, l);
+            rg_1q<b>(v, g.m);
+            rg_1q<b>(l, g.m);
+        });
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if ((tid & 63) == 0) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
+    } else {
+        apply_gate<RB>(v, g);
+        apply_gate<RB>(l, g);
+    }
+}
+
+// One two-vector tile pass.  partials: this pass's block of
+// [tile][slot][wave] doubles (slot count in the header's pad field).
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __restrict__ psi,
+                                                       typename V2T<R>::type* __restrict__ lam,
+                                                       const char* __restrict__ plan,
+                                                       double* __restrict__ partials) {
+    using V = typename V2T<R>::type;
+    constexpr int E = 1 << K;
+    constexpr int RB = K - 8;
+    constexpr int P = 1 << RB;
+    constexpr uint32_t ES = sizeof(V);
+    __shared__ V tp[E];
+    __shared__ V tl[E];
+    char* lp = reinterpret_cast<char*>(tp);
+    char* ll = reinterpret_cast<char*>(tl);
+
+    const TPassHdr* hdr = reinterpret_cast<const TPassHdr*>(plan);
+    const TStage* stg = reinterpret_cast<const TStage*>(plan + sizeof(TPassHdr));
+    const int nst = hdr->nstages;
+    const int nslot = hdr->pad;
+    const TGate<R>* gates = reinterpret_cast<const TGate<R>*>(plan + sizeof(TPassHdr) +
+                                                              size_t(nst) * sizeof(TStage));
+    const uint32_t tid = threadIdx.x;
+    double* const part_out = partials + size_t(blockIdx.x) * size_t(nslot) * 4;
+
+    uint64_t b = blockIdx.x;
+#pragma unroll
+    for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
+    const uint64_t xt = b | deposit(tid, hdr->pos, 8);
+    V* const sp = psi + xt;
+    V* const sl = lam + xt;
+    V v[P], l[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        v[u] = sp[hdr->du[u]];
+        l[u] = sl[hdr->du[u]];
+    }
+    for (int st = 0; st < nst; ++st) {
+        const TStage& S = stg[st];
+        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
+        if (st > 0) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                v[u] = *reinterpret_cast<const V*>(lp + (sb ^ S.su[u]));
+                l[u] = *reinterpret_cast<const V*>(ll + (sb ^ S.su[u]));
+            }
+        }
+        for (int g = S.gbeg; g < S.gend; ++g) apply_gate2<RB>(v, l, gates[g], part_out, tid);
+        if (st < nst - 1) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                *reinterpret_cast<V*>(lp + (sb ^ S.su[u])) = v[u];
+                *reinterpret_cast<V*>(ll + (sb ^ S.su[u])) = l[u];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        sp[hdr->du[u]] = v[u];
+        sl[hdr->du[u]] = l[u];
+    }
+}
+
+// grad[tag[s]] = sum over (tile, wave) of partials[(tile * nslot + s) * 4 + wave], fixed order
+__global__ __launch_bounds__(kThreads) void k_adj_cols(const double* __restrict__ partials,
+                                                       int tiles, int nslot,
+                                                       const int32_t* __restrict__ tags,
+                                                       double* __restrict__ grad) {
+    __shared__ double red[1][kThreads];
+    const int s = blockIdx.x;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < tiles; t += kThreads) {
+        const double* p = partials + (size_t(t) * nslot + s) * 4;
+        acc += (p[0] + p[1]) + (p[2] + p[3]);
+    }
+    red[0][threadIdx.x] = acc;
+    double tot[1];
+    block_tree256<1>(red, tot);
+    if (threadIdx.x == 0) grad[tags[s]] = tot[0];
+}
+
+template <typename R, int K>
+hipError_t launch_adj_tile(qsv_ctx ctx, void* psi, void* lam, int n, const char* rec,
+                           double* partials) {
+    using V = typename V2T<R>::type;
+    const unsigned tiles = unsigned(uint64_t(1) << (n - K));
+    hipLaunchKernelGGL((k_adj_tile<R, K>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
+                       static_cast<V*>(psi), static_cast<V*>(lam), rec, partials);
+    return hipGetLastError();
+}
+
+template <typename R>
+constexpr int adj_tile_bits() { return sizeof(R) == 8 ? 11 : 12; }   // two tiles: 64 KiB of LDS
+
 void dagger(const PGate& g, PGate& d) {
     d = g;
     const int n = g.kind == QSV_G2Q ? 4 : 2;
@@ -102,13 +247,60 @@ void dagger(const PGate& g, PGate& d) {
 }
 
 template <typename R>
+hipError_t rewind_one(qsv_ctx ctx, void* psi, void* lam, int n, const PGate& g, int axis,
+                      double* dgrad_slot) {
+    using V = typename V2T<R>::type;
+    const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
+    const uint64_t N = uint64_t(1) << n;
+    PGate d;
+    dagger(g, d);
+    if (axis < 0) {
+        hipError_t e = launch_gate(ctx, psi, n, dt, d);
+        if (e != hipSuccess) return e;
+        return launch_gate(ctx, lam, n, dt, d);
+    }
+    const uint64_t npairs = N / 2;
+    const unsigned G = adj_blocks(npairs);
+    const uint64_t chunk = (npairs + G - 1) / G;
+    M2<R> ud;
+    for (int i = 0; i < 8; ++i) ud.v[i] = R(d.m[i]);
+    prof_before(ctx, sizeof(R) == 8 ? "adj_rot_c128" : "adj_rot_c64", 4.0 * double(N) * sizeof(V));
+    switch (axis) {
+    case QSV_AXIS_X:
+        hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_X>), dim3(G), dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(psi), static_cast<V*>(lam), npairs, chunk, g.p0, ud,
+                           ctx->d_red);
+        break;
+    case QSV_AXIS_Y:
+        hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_Y>), dim3(G), dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(psi), static_cast<V*>(lam), npairs, chunk, g.p0, ud,
+                           ctx->d_red);
+        break;
+    default:
+        hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_Z>), dim3(G), dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(psi), static_cast<V*>(lam), npairs, chunk, g.p0, ud,
+                           ctx->d_red);
+        break;
+    }
+    prof_after(ctx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kThreads), 0, ctx->stream, ctx->d_red, int(G),
+                       dgrad_slot);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector<PGate>& fwd,
                      const std::vector<int>& rot_param, const std::vector<int>& rot_axis,
-                     int nterms, const uint64_t* pmasks, const double* w, double* grad_by_gate) {
+                     int nterms, const uint64_t* pmasks, const double* w, double* grad_by_gate,
+                     bool fused) {
     using V = typename V2T<R>::type;
     const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
     const uint64_t N = uint64_t(1) << n;
     const size_t ng = fwd.size();
+    constexpr int KA = adj_tile_bits<R>();
+    if (n < KA) fused = false;
 
     // observable upload: masks then weights
     const size_t obytes = size_t(nterms) * (sizeof(uint64_t) + sizeof(double));
@@ -124,10 +316,6 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
     const uint64_t* dmask = static_cast<const uint64_t*>(dev);
     const double* dw = reinterpret_cast<const double*>(static_cast<char*>(dev) +
                                                        size_t(nterms) * sizeof(uint64_t));
-    e = ensure_aux(ctx, ng + 1);
-    if (e != hipSuccess) return e;
-    double* dgrad = ctx->d_aux;
-
     prof_before(ctx, sizeof(R) == 8 ? "adj_obs_c128" : "adj_obs_c64", 2.0 * double(N) * sizeof(V));
     hipLaunchKernelGGL(k_apply_obs<R>, dim3(unsigned((N + kThreads - 1) / kThreads)), dim3(kThreads),
                        0, ctx->stream, static_cast<const V*>(psi), static_cast<V*>(lam), N, nterms,
@@ -135,51 +323,105 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
     prof_after(ctx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    const uint64_t npairs = N / 2;
-    const unsigned G = adj_blocks(npairs);
-    const uint64_t chunk = (npairs + G - 1) / G;
     bool any_rot = false;
-    for (size_t kk = ng; kk-- > 0;) {
-        const PGate& g = fwd[kk];
-        PGate d;
-        dagger(g, d);
-        if (rot_param[kk] >= 0) {
-            any_rot = true;
-            M2<R> ud;
-            for (int i = 0; i < 8; ++i) ud.v[i] = R(d.m[i]);
-            prof_before(ctx, sizeof(R) == 8 ? "adj_rot_c128" : "adj_rot_c64",
-                        4.0 * double(N) * sizeof(V));
-            switch (rot_axis[kk]) {
-            case QSV_AXIS_X:
-                hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_X>), dim3(G), dim3(kThreads), 0,
-                                   ctx->stream, static_cast<V*>(psi), static_cast<V*>(lam), npairs,
-                                   chunk, g.p0, ud, ctx->d_red);
-                break;
-            case QSV_AXIS_Y:
-                hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_Y>), dim3(G), dim3(kThreads), 0,
-                                   ctx->stream, static_cast<V*>(psi), static_cast<V*>(lam), npairs,
-                                   chunk, g.p0, ud, ctx->d_red);
-                break;
-            default:
-                hipLaunchKernelGGL((k_adj_rot<R, QSV_AXIS_Z>), dim3(G), dim3(kThreads), 0,
-                                   ctx->stream, static_cast<V*>(psi), static_cast<V*>(lam), npairs,
-                                   chunk, g.p0, ud, ctx->d_red);
-                break;
+    for (size_t kk = 0; kk < ng; ++kk) any_rot |= rot_param[kk] >= 0;
+
+    if (!fused) {
+        e = ensure_aux(ctx, ng + 1);
+        if (e != hipSuccess) return e;
+        for (size_t kk = ng; kk-- > 0;) {
+            e = rewind_one<R>(ctx, psi, lam, n, fwd[kk], rot_param[kk] >= 0 ? rot_axis[kk] : -1,
+                              ctx->d_aux + kk);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        // the reversed, daggered circuit; rotations kept as KROT with their forward index
+        std::vector<PGate> rev;
+        rev.reserve(ng);
+        for (size_t kk = ng; kk-- > 0;) {
+            PGate d;
+            dagger(fwd[kk], d);
+            if (rot_param[kk] >= 0) {
+                d.kind = KROT;
+                d.cs = rot_axis[kk];
+                d.tag = int(kk);
             }
+            rev.push_back(d);
+        }
+        rev = prefuse(rev);
+        std::vector<Pass> passes = plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4});
+        // slots, record layout, partial-buffer size
+        size_t bytes = 0, max_part = 0;
+        std::vector<size_t> offs(passes.size(), 0), tag_off(passes.size(), 0);
+        std::vector<int> nslot(passes.size(), 0);
+        for (size_t i = 0; i < passes.size(); ++i) {
+            Pass& ps = passes[i];
+            if (ps.single) continue;
+            int s = 0;
+            for (int gi : ps.gates)
+                if (rev[size_t(gi)].kind == KROT) rev[size_t(gi)].p1 = s++;
+            nslot[i] = s;
+            offs[i] = bytes;
+            bytes += pass_record_bytes(dt, ps);
+            tag_off[i] = bytes;
+            bytes += (size_t(s) * sizeof(int32_t) + 255) & ~size_t(255);
+            const size_t part = (size_t(1) << (n - KA)) * size_t(s) * 4;
+            if (part > max_part) max_part = part;
+        }
+        e = ensure_aux(ctx, ng + 1 + max_part);
+        if (e != hipSuccess) return e;
+        double* dgrad = ctx->d_aux;
+        double* dpart = ctx->d_aux + ng + 1;
+        char* drec = nullptr;
+        if (bytes) {
+            e = plan_staging(ctx, bytes, &host);
+            if (e != hipSuccess) return e;
+            char* h = static_cast<char*>(host);
+            for (size_t i = 0; i < passes.size(); ++i) {
+                const Pass& ps = passes[i];
+                if (ps.single) continue;
+                if (!write_pass_record(dt, h + offs[i], rev, ps)) return hipErrorInvalidValue;
+                reinterpret_cast<TPassHdr*>(h + offs[i])->pad = nslot[i];
+                int32_t* tags = reinterpret_cast<int32_t*>(h + tag_off[i]);
+                for (int gi : ps.gates)
+                    if (rev[size_t(gi)].kind == KROT) tags[rev[size_t(gi)].p1] = rev[size_t(gi)].tag;
+            }
+            e = plan_upload(ctx, bytes, &dev);
+            if (e != hipSuccess) return e;
+            drec = static_cast<char*>(dev);
+        }
+        const int tiles = int(uint64_t(1) << (n - KA));
+        for (size_t i = 0; i < passes.size(); ++i) {
+            const Pass& ps = passes[i];
+            if (ps.single) {
+                const PGate& g = rev[size_t(ps.gates[0])];
+                if (g.kind == KROT) {
+                    // rewind_one daggers its argument: hand it the forward gate
+                    e = rewind_one<R>(ctx, psi, lam, n, fwd[size_t(g.tag)], g.cs, dgrad + g.tag);
+                } else {
+                    e = launch_gate(ctx, psi, n, dt, g);
+                    if (e == hipSuccess) e = launch_gate(ctx, lam, n, dt, g);
+                }
+                if (e != hipSuccess) return e;
+                continue;
+            }
+            prof_before(ctx, sizeof(R) == 8 ? "adj_tile_c128" : "adj_tile_c64",
+                        4.0 * double(N) * sizeof(V));
+            e = launch_adj_tile<R, KA>(ctx, psi, lam, n, drec + offs[i], dpart);
             prof_after(ctx);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kThreads), 0, ctx->stream, ctx->d_red,
-                               int(G), dgrad + kk);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        } else {
-            if ((e = launch_gate(ctx, psi, n, dt, d)) != hipSuccess) return e;
-            if ((e = launch_gate(ctx, lam, n, dt, d)) != hipSuccess) return e;
+            if (e != hipSuccess) return e;
+            if (nslot[i] > 0) {
+                hipLaunchKernelGGL(k_adj_cols, dim3(unsigned(nslot[i])), dim3(kThreads), 0,
+                                   ctx->stream, dpart, tiles, nslot[i],
+                                   reinterpret_cast<const int32_t*>(drec + tag_off[i]), dgrad);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
         }
     }
     for (size_t kk = 0; kk < ng; ++kk) grad_by_gate[kk] = 0.0;
     if (any_rot) {
         std::vector<double> tmp(ng, 0.0);
-        e = hipMemcpyAsync(tmp.data(), dgrad, ng * sizeof(double), hipMemcpyDeviceToHost,
+        e = hipMemcpyAsync(tmp.data(), ctx->d_aux, ng * sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(ctx->stream);
@@ -198,12 +440,12 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
 hipError_t run_adjoint(qsv_ctx ctx, void* psi, void* lam, int n, int dtype,
                        const std::vector<PGate>& fwd, const std::vector<int>& rot_param,
                        const std::vector<int>& rot_axis, int nterms, const uint64_t* pmasks,
-                       const double* w, double* grad_by_gate) {
+                       const double* w, double* grad_by_gate, bool fused) {
     return dtype == QSV_C128
                ? adjoint_t<double>(ctx, psi, lam, n, fwd, rot_param, rot_axis, nterms, pmasks, w,
-                                   grad_by_gate)
+                                   grad_by_gate, fused)
                : adjoint_t<float>(ctx, psi, lam, n, fwd, rot_param, rot_axis, nterms, pmasks, w,
-                                  grad_by_gate);
+                                  grad_by_gate, fused);
 }
 
 }  // namespace qsv

@@ -310,7 +310,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
                 for (int gi : ps.gates) {
                     const PGate& x = lowered[size_t(c)][size_t(gi)];
                     need |= uint64_t(1) << loc[x.p0];
-                    if (x.kind != QSV_G1Q) need |= uint64_t(1) << loc[x.p1];
+                    if (!is_1q(x.kind)) need |= uint64_t(1) << loc[x.p1];
                 }
                 if (need & 0xFF) {   // a low local bit: use a register set holding the gate's bits
                     int j = 0;

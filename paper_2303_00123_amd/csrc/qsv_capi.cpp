@@ -605,7 +605,8 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
     std::vector<double> by_gate(size_t(ng), 0.0);
     HIP_OR_FAIL(ctx,
                 run_adjoint(ctx, psi->ptr, lam->ptr, n, psi->dtype, fwd, rot_param, rot_axis,
-                            nterms, pm.data(), wv.data(), by_gate.data()),
+                            nterms, pm.data(), wv.data(), by_gate.data(),
+                            !(flags & QSV_FLAG_NO_FUSE)),
                 "adjoint sweep");
     for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
     for (int64_t i = 0; i < ng; ++i)

@@ -20,11 +20,18 @@ inline size_t amp_bytes(int dtype) { return dtype == QSV_C128 ? 16 : 8; }
 // ---------------------------------------------------------------- plans
 // A gate in index-bit coordinates: position p = n-1-q of qubit q.
 struct PGate {
-    int kind;       // QSV_G1Q, QSV_GC1Q, QSV_G2Q (rotations are lowered to G1Q)
+    int kind;       // QSV_G1Q, QSV_GC1Q, QSV_G2Q (rotations are lowered to G1Q), or KROT
     int p0, p1;     // G1Q: p0 target; GC1Q: p0 control, p1 target; G2Q: p0 = pos(qa), p1 = pos(qb)
     int cs;
     double m[32];
+    int tag = -1;   // adjoint sweep: index of the forward gate a KROT rewinds
 };
+
+// Internal kind for the adjoint sweep: a rotation exp(-i theta P/2) being
+// rewound.  p0 = target, cs = Pauli axis, p1 = its partial-sum slot in the
+// pass, m = the 2x2 U^dagger.  Never fused with other gates.
+constexpr int KROT = 16;
+inline bool is_1q(int kind) { return kind == QSV_G1Q || kind == KROT; }
 
 // A stage of a tile pass: the gates applied while each thread holds the
 // amplitudes spanning `rbits` (local tile bits) in registers.
@@ -74,7 +81,8 @@ enum {
     DK_C1Q = 2,   // generic 2x2 on r1 where register bit r0 == cs
     DK_CX = 3,    // swap on r1 where r0 == cs (controlled X)
     DK_CD = 4,    // diagonal (d0, d1) on r1 where r0 == cs
-    DK_2Q = 5     // generic 4x4 on (r0, r1), local index 2*x_r0 + x_r1
+    DK_2Q = 5,    // generic 4x4 on (r0, r1), local index 2*x_r0 + x_r1
+    DK_ROT = 6    // adjoint sweep: partial Im<lam|P|psi> into slot r1, then 2x2 m on r0; P = axis cs
 };
 
 // Device-side gate record of a tile pass (register bit coordinates).
@@ -234,10 +242,11 @@ hipError_t reduce_inner(qsv_ctx ctx, const void* a, int dta, const void* b, int 
 // keep amplitudes whose bit p equals `keep`, scaled by `scale`; zero the rest.
 hipError_t launch_collapse(qsv_ctx ctx, void* s, int n, int dtype, int p, int keep, double scale);
 
-// Adjoint sweep (qsv_adjoint.hip).
+// Adjoint sweep (qsv_adjoint.hip).  fused: rewind through two-vector tile
+// passes; otherwise one kernel per gate.
 hipError_t run_adjoint(qsv_ctx ctx, void* psi, void* lam, int n, int dtype,
                        const std::vector<PGate>& fwd, const std::vector<int>& rot_param,
                        const std::vector<int>& rot_axis, int nterms, const uint64_t* pmasks,
-                       const double* w, double* grad_by_gate);
+                       const double* w, double* grad_by_gate, bool fused);
 
 }  // namespace qsv

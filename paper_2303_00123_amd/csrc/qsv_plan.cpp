@@ -29,7 +29,7 @@ namespace qsv {
 
 static inline uint64_t gate_mask(const PGate& g) {
     uint64_t m = uint64_t(1) << g.p0;
-    if (g.kind != QSV_G1Q) m |= uint64_t(1) << g.p1;
+    if (!is_1q(g.kind)) m |= uint64_t(1) << g.p1;
     return m;
 }
 
@@ -71,7 +71,7 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     for (int gi : ps.gates) {
         const PGate& g = gates[size_t(gi)];
         uint64_t m = uint64_t(1) << loc[g.p0];
-        if (g.kind != QSV_G1Q) m |= uint64_t(1) << loc[g.p1];
+        if (!is_1q(g.kind)) m |= uint64_t(1) << loc[g.p1];
         lm[size_t(gi)] = m;
     }
     const uint64_t canon = ((uint64_t(1) << K) - 1) & ~uint64_t(0xFF);   // local bits 8..K-1
@@ -205,6 +205,24 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
 
     for (int gi : idx) {
         const PGate& g = gates[size_t(gi)];
+        if (g.kind == KROT) {
+            // kept whole: flush a pending 1-qubit product on its qubit first
+            if (has[g.p0]) {
+                PGate f{};
+                f.kind = QSV_G1Q;
+                f.p0 = g.p0;
+                f.cs = 1;
+                for (int i = 0; i < 4; ++i) {
+                    f.m[2 * i] = pend[g.p0][i].real();
+                    f.m[2 * i + 1] = pend[g.p0][i].imag();
+                }
+                out.push_back(f);
+                has[g.p0] = false;
+            }
+            out.push_back(g);
+            last[g.p0] = int(out.size()) - 1;
+            continue;
+        }
         if (g.kind == QSV_G1Q) {
             cd u[4];
             m2_from(g.m, u);
@@ -222,7 +240,7 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
         int prev = -1;
         if (last[a] >= 0 && last[a] == last[b]) {
             const PGate& o = out[size_t(last[a])];
-            if (o.kind != QSV_G1Q && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a))) prev = last[a];
+            if (!is_1q(o.kind) && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a))) prev = last[a];
         }
         if (!absorb && prev < 0) {
             out.push_back(g);

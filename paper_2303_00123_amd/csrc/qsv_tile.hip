@@ -73,10 +73,17 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
     for (int j = 0; j < st.nr; ++j) reg[st.rbits[j]] = j;
     for (int m = 0; m < 32; ++m) t.m[m] = R(0);
     t.cs = 1;
-    if (loc[g.p0] < 0 || (g.kind != QSV_G1Q && loc[g.p1] < 0)) return false;
+    if (loc[g.p0] < 0 || (!is_1q(g.kind) && loc[g.p1] < 0)) return false;
     t.r0 = reg[loc[g.p0]];
-    t.r1 = g.kind == QSV_G1Q ? 0 : reg[loc[g.p1]];
-    if (t.r0 < 0 || t.r1 < 0 || (g.kind != QSV_G1Q && t.r0 == t.r1)) return false;
+    t.r1 = is_1q(g.kind) ? 0 : reg[loc[g.p1]];
+    if (t.r0 < 0 || t.r1 < 0 || (!is_1q(g.kind) && t.r0 == t.r1)) return false;
+    if (g.kind == KROT) {
+        t.kind = DK_ROT;
+        t.r1 = g.p1;    // partial-sum slot
+        t.cs = g.cs;    // axis
+        for (int i = 0; i < 8; ++i) t.m[i] = R(g.m[i]);
+        return true;
+    }
     const double* m = g.m;
     double m4[32];
     int kind = g.kind;

@@ -1,0 +1,88 @@
+"""Adjoint-gradient sweep: fused two-vector tile passes vs one kernel per
+gate vs the FP64 oracle (adjoint and parameter shift), and the 24-qubit
+configuration against parameter shift evaluated with the GPU forward pass."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2303_00123_amd as qq
+    return qq
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context()
+    yield c
+    c.close()
+
+
+def wsum(c):
+    return max(1.0, sum(abs(w) for _, w in c.observable))
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.hea_cz_ring(12, 3, seed=12),
+    lambda: W.hea_cz_ring(14, 4, seed=14, ring_obs=True),
+    lambda: W.ry_rz_cnot_ladder(15, 3, np.random.default_rng(15)),
+])
+def test_fused_adjoint_vs_unfused_and_oracle(q, ctx, maker):
+    c = maker()
+    f_ref, g_ref = O.adjoint(c)
+    psi, lam = q.State(ctx, c.n), q.State(ctx, c.n)
+    f1, g1 = q.adjoint(psi, lam, c.gates, c.params, c.observable)                     # fused
+    f2, g2 = q.adjoint(psi, lam, c.gates, c.params, c.observable,
+                       flags=q.FLAG_FORWARD | q.FLAG_NO_FUSE)                         # unfused
+    tol = 1e-10 * wsum(c)
+    assert abs(f1 - f_ref) <= 1e-12 * wsum(c) and abs(f2 - f_ref) <= 1e-12 * wsum(c)
+    assert np.max(np.abs(g1 - g_ref)) <= tol
+    assert np.max(np.abs(g2 - g_ref)) <= tol
+    sel = list(range(0, len(c.params), 7))
+    assert np.max(np.abs(g1[sel] - O.param_shift(c, sel))) <= tol
+    # psi is rewound to |0...0>
+    v = psi.to_numpy()
+    assert abs(v[0] - 1.0) <= 1e-10 and abs(np.linalg.norm(v) - 1.0) <= 1e-10
+    p64, l64 = q.State(ctx, c.n, q.QSV_C64), q.State(ctx, c.n, q.QSV_C64)
+    f3, g3 = q.adjoint(p64, l64, c.gates, c.params, c.observable)
+    assert np.max(np.abs(g3 - g_ref)) <= 1e-4 * wsum(c)
+
+
+def test_config5_adjoint_vs_gpu_parameter_shift(q, ctx):
+    """24 qubits, 10 layers RY,RZ + CZ ring, 480 parameters: the fused adjoint
+    gradient against parameter shift on 24 sampled parameters, each shifted
+    energy evaluated with the (oracle-validated) GPU forward pass."""
+    c = W.config5()
+    psi, lam = q.State(ctx, c.n), q.State(ctx, c.n)
+    f, g = q.adjoint(psi, lam, c.gates, c.params, c.observable)
+    g_unf = q.adjoint(psi, lam, c.gates, c.params, c.observable,
+                      flags=q.FLAG_FORWARD | q.FLAG_NO_FUSE)[1]
+    marsh = q.marshal_gates(c.gates)
+
+    def energy(params):
+        psi.init_basis(0)
+        psi.apply_circuit(None, params, marshalled=marsh)
+        return psi.expect_z(c.observable)[1]
+
+    assert abs(energy(c.params) - f) <= 1e-11 * wsum(c)
+    rng = np.random.default_rng(55)
+    sel = rng.choice(len(c.params), size=24, replace=False)
+    for j in sel:
+        p = c.params.copy()
+        p[j] += np.pi / 2
+        fp = energy(p)
+        p[j] -= np.pi
+        fm = energy(p)
+        assert abs(g[j] - 0.5 * (fp - fm)) <= 1e-10 * wsum(c), j
+    assert np.max(np.abs(g - g_unf)) <= 1e-11 * wsum(c)
+    p64, l64 = q.State(ctx, c.n, q.QSV_C64), q.State(ctx, c.n, q.QSV_C64)
+    g64 = q.adjoint(p64, l64, c.gates, c.params, c.observable)[1]
+    assert np.max(np.abs(g64 - g)) <= 1e-4 * wsum(c)

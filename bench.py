@@ -171,15 +171,19 @@ def batch_bench(q, W, dtype, reps: int = 5):
     in one persistent launch: wall time per call (host planning included) and
     the kernel time of the replayed hipGraph."""
     import torch
+    import numpy as np
     circs = W.config4()
+    spec = q.BatchSpec(circs)
     ctx = q.Context()
-    ctx.batch_run(circs, dtype, flags=q.FLAG_TUNE)
-    ctx.batch_run(circs, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+    ctx.batch_run(spec, dtype, flags=q.FLAG_TUNE)
+    ctx.batch_run(spec, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+    rng = np.random.default_rng(4999)
+    angle_sets = [rng.uniform(0, 2 * np.pi, size=spec.params.size) for _ in range(reps)]
     torch.cuda.synchronize()
     ctx.profile_begin()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        ctx.batch_run(circs, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+    for a in angle_sets:   # new angles every call, same circuit structure
+        ctx.batch_run(spec, dtype, flags=q.FLAG_CAPTURE_GRAPH, params=a)
     t1 = time.perf_counter()
     prof = ctx.profile_end()
     ctx.close()

@@ -253,13 +253,16 @@ qsv_status qsv_profile_begin(qsv_ctx ctx);
 qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
 
 /* Tile shape of the context's later fused passes for one dtype.
- * tile_bits: log2 of the amplitudes per tile, in [10, 12] for QSV_C128 and
- * [10, 13] for QSV_C64 (0 = the default, 12).  States with fewer than 10 qubits
- * run one kernel per gate.  low_bits: number of lowest index
- * bits every tile keeps, so each tile is made of contiguous runs of
- * 2^low_bits amplitudes; in [0, tile_bits - 2] (0 = 3 for QSV_C128, 4 for
- * QSV_C64, i.e. 128-byte runs). */
-qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits);
+ * tile_bits: log2 of the amplitudes per tile, in [10, 13] (0 = the default, 12).
+ * low_bits: number of lowest index bits every tile keeps, so each tile is
+ * made of contiguous runs of 2^low_bits amplitudes; in [0, tile_bits - 2]
+ * (0 = 3 for QSV_C128, 4 for QSV_C64, i.e. 128-byte runs).
+ * reg_bits: log2 of the amplitudes each thread keeps in registers (a tile
+ * has 2^(tile_bits - reg_bits) threads; 0 = 4 for tiles of 2^12 or more,
+ * else tile_bits - 8).  Compiled (tile_bits, reg_bits) shapes: (10, 2),
+ * (11, 3), (12, 3), (12, 4), (13, 4), (13, 5); others give QSV_ERR_ARG.
+ * States with fewer than 10 qubits run one kernel per gate. */
+qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits);
 
 /* Host-only query of the exact gate sequence the tile kernels would apply for
  * qsv_apply_circuit (no device work; needs no GPU): gates grouped into passes
@@ -270,8 +273,8 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits);
  * output may be NULL); *nout receives the number of records, or the number
  * needed if cap is too small (then QSV_ERR_SIZE). */
 qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
-                          int64_t nparams, int tile_bits, int low_bits, qsv_gate* out, int64_t cap,
-                          int32_t* pass_of_out, int64_t* nout);
+                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, qsv_gate* out,
+                          int64_t cap, int32_t* pass_of_out, int64_t* nout);
 
 /* Host-only query of the fusion plan qsv_apply_circuit would use for an
  * n-qubit circuit (no device work; needs no GPU).  tile_bits / low_bits as in
@@ -281,7 +284,7 @@ qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const
  * pass, its register stages in sequence); pass_qubits[p] = qubit mask (bit q = qubit q)
  * of pass p's tile.  *npasses receives the number of passes. */
 qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int tile_bits,
-                            int low_bits, int64_t* npasses, int32_t* pass_of_gate,
+                            int low_bits, int reg_bits, int64_t* npasses, int32_t* pass_of_gate,
                             int32_t* exec_order, uint64_t* pass_qubits);
 
 #ifdef __cplusplus

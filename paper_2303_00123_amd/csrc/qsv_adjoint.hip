@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     uint64_t b = blockIdx.x;
 #pragma unroll
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
-    const uint64_t xt = b | deposit(tid, hdr->pos, 8);
+    const uint64_t xt = b | deposit(tid, hdr->tpos_ld, 8);
     V* const sp = psi + xt;
     V* const sl = lam + xt;
     V v[P], l[P];
@@ -198,10 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
             __syncthreads();
         }
     }
+    const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);
+    V* const sq = psi + xs;
+    V* const sm = lam + xs;
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-        sp[hdr->du[u]] = v[u];
-        sl[hdr->du[u]] = l[u];
+        sq[hdr->du_st[u]] = v[u];
+        sm[hdr->du_st[u]] = l[u];
     }
 }
 
@@ -349,7 +352,7 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
             rev.push_back(d);
         }
         rev = prefuse(rev);
-        std::vector<Pass> passes = plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4});
+        std::vector<Pass> passes = plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt)});
         // slots, record layout, partial-buffer size
         size_t bytes = 0, max_part = 0;
         std::vector<size_t> offs(passes.size(), 0), tag_off(passes.size(), 0);

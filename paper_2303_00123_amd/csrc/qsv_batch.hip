@@ -21,6 +21,7 @@
 // (the per-XCD L2s are not coherent with each other) uses agent-scope
 // release/acquire on the per-circuit completion counters.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -104,8 +105,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
         uint64_t b = uint32_t(I.tile);
 #pragma unroll
         for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
-        const uint64_t xt = b | deposit(tid, hdr->pos, 8);   // index of register slot 0
+        const uint64_t xt = b | deposit(tid, hdr->tpos_ld, 8);   // register slot 0 (load mapping)
+        const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);   // register slot 0 (store mapping)
         V* const sp = states + C.state_off + xt;
+        V* const sq = states + C.state_off + xs;
 
         V v[P];
         bool ok = true;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
                 for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
             }
         }
-        if (ok) run_stages<R, K>(v, lds, stg, nst, gates, tid);
+        if (ok) run_stages<R, K, K - 8>(v, lds, stg, nst, gates, tid);
 
         if (Pp.flags & BP_LAST) {
             double acc = 0.0;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
                 for (int u = 0; u < P; ++u) {
                     const double re = double(v[u].x), im = double(v[u].y);
                     acc += (re * re + im * im) *
-                           zsign_sum(xt | hdr->du[u], tmask, tw, C.term_beg, C.term_end);
+                           zsign_sum(xs | hdr->du_st[u], tmask, tw, C.term_beg, C.term_end);
                 }
             }
             red[0][tid] = acc;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
         } else {
             if (ok) {
 #pragma unroll
-                for (int u = 0; u < P; ++u) sp[hdr->du[u]] = v[u];
+                for (int u = 0; u < P; ++u) sq[hdr->du_st[u]] = v[u];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
@@ -256,7 +259,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             pg.push_back(p);
         }
         pg = prefuse(pg);
-        plans[size_t(c)] = plan_passes(ne, pg, TileConfig{K, L});
+        plans[size_t(c)] = plan_passes(ne, pg, TileConfig{K, L, K - 8, coal_bits_for(dtype)});
         // a pass of one gate would run as an unfused kernel in the single-state
         // path; here every pass is a tile pass, so give singletons their stages
         BCirc bc{};
@@ -266,6 +269,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             // no gates: still one (empty) pass to produce the observable
             Pass ps;
             ps.k = K;
+            ps.rb = K - 8;
             for (int b = 0; b < K; ++b) ps.pos[b] = b;
             plans[size_t(c)].push_back(ps);
             bc.npasses = 1;
@@ -299,6 +303,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
                 // one-gate (or empty) pass: a single canonical stage holding it
                 ps.single = false;
                 ps.stages.clear();
+                ps.rb = K - 8;
                 Stage st;
                 st.nr = K - 8;
                 for (int j = 0; j < st.nr; ++j) st.rbits[j] = 8 + j;
@@ -566,6 +571,27 @@ static qsv_status finish_batch(qsv_ctx ctx, hipStream_t stream, int nb, double* 
     return QSV_OK;
 }
 
+// Key of a batch's shape: qubit counts, gate kinds / qubits / control states /
+// axes and observable masks -- everything but angles, matrices and weights.
+static uint64_t shape_key(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
+                          const int64_t* term_off, const uint64_t* qmasks, int dtype) {
+    uint64_t h = 1469598103934665603ull;
+    mix(h, uint64_t(nb));
+    mix(h, uint64_t(dtype));
+    for (int c = 0; c < nb; ++c) {
+        mix(h, uint64_t(nq[c]));
+        for (int64_t i = gate_off[c]; i < gate_off[c + 1]; ++i) {
+            const qsv_gate& G = g[i];
+            mix(h, uint64_t(uint32_t(G.kind)) | (uint64_t(uint32_t(G.q0)) << 8) |
+                       (uint64_t(uint32_t(G.q1)) << 20) | (uint64_t(G.ctrl_state & 1) << 32) |
+                       (uint64_t(G.axis & 3) << 33));
+        }
+        for (int64_t t = term_off[c]; t < term_off[c + 1]; ++t) mix(h, qmasks[t]);
+        mix(h, 0x5eedull);
+    }
+    return h;
+}
+
 // Tile shapes the autotuner tries for a batch, best first by default.
 static const int kTuneShapes[][2] = {{12, 3}, {11, 3}, {10, 2}, {12, 4}, {11, 2}, {10, 3}};
 
@@ -616,11 +642,8 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
     uint64_t key = 0;
     int K = 12, L = dtype == QSV_C128 ? 3 : 4;
     {
-        // shape key without the tile shape, to look up a tuned choice
-        BatchRun R0;
-        qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
-                                   dtype, K, L, R0, key);
-        if (s != QSV_OK) return s;
+        key = shape_key(nb, nq, gate_off, g, term_off, qmasks, dtype);
+        qsv_status s = QSV_OK;
         int tk = 0, tl = 0;
         if (tune_lookup(ctx, key, dtype, &tk, &tl)) {
             K = tk;
@@ -659,9 +682,15 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
             tune_store(ctx, key, dtype, K, L, best);
         }
     }
+    const auto t0 = std::chrono::steady_clock::now();
     qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
                                dtype, K, L, R, key);
     if (s != QSV_OK) return s;
+    if (log_enabled()) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        logf("batch: %d circuits, %d items, tile 2^%d low %d, plan %zu B, states %zu B, host planning %.2f ms",
+             nb, R.nitems, K, L, R.L.total, R.state_bytes, ms);
+    }
     hipError_t e;
     if (flags & QSV_FLAG_CAPTURE_GRAPH) {
         if (!ctx->batch_stream) {

@@ -443,8 +443,19 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
         return QSV_OK;
     }
     const TileConfig& cfg = st->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    const size_t ng_in = pg.size();
     pg = prefuse(pg);
     std::vector<Pass> passes = plan_passes(st->n, pg, cfg);
+    if (log_enabled()) {
+        size_t stages = 0, singles = 0;
+        for (const Pass& p : passes) {
+            stages += p.stages.size();
+            singles += p.single ? 1 : 0;
+        }
+        logf("apply_circuit: n=%d %zu gates -> %zu after fusion, %zu passes (%zu single-gate), "
+             "%zu register stages, tile 2^%d low %d",
+             st->n, ng_in, pg.size(), passes.size(), singles, stages, cfg.tile_bits, cfg.low_bits);
+    }
     HIP_OR_FAIL(ctx, run_passes(ctx, st->ptr, st->n, st->dtype, pg, passes), "tile passes");
     return QSV_OK;
 }
@@ -616,33 +627,48 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
 }
 
 // ------------------------------------------------------------------ tuning
-qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits) {
-    if (!ctx) return QSV_ERR_ARG;
-    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
-    TileConfig& cfg = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+static qsv_status tile_config(int dtype, int tile_bits, int low_bits, int reg_bits, TileConfig& out,
+                              std::string& err) {
     const int kmax = tile_bits_max(dtype);
     const int tb = tile_bits ? tile_bits : kDefaultTileBits;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    if (tb < kMinTileBits || tb > kmax)
-        return fail(ctx, QSV_ERR_ARG, "tile_bits must be in [" + std::to_string(kMinTileBits) + ", " +
-                                          std::to_string(kmax) + "]");
-    if (lb < 0 || lb > tb - 2) return fail(ctx, QSV_ERR_ARG, "low_bits must be in [0, tile_bits-2]");
-    cfg.tile_bits = tb;
-    cfg.low_bits = lb;
+    const int rb = reg_bits ? reg_bits : (tb >= 12 ? kDefaultRegBits : tb - 8);
+    if (tb < kMinTileBits || tb > kmax) {
+        err = "tile_bits must be in [" + std::to_string(kMinTileBits) + ", " + std::to_string(kmax) + "]";
+        return QSV_ERR_ARG;
+    }
+    if (lb < 0 || lb > tb - 2) {
+        err = "low_bits must be in [0, tile_bits-2]";
+        return QSV_ERR_ARG;
+    }
+    if (!tile_shape_supported(dtype, tb, rb)) {
+        err = "no tile kernel for tile_bits " + std::to_string(tb) + " with reg_bits " + std::to_string(rb);
+        return QSV_ERR_ARG;
+    }
+    out = TileConfig{tb, lb, rb, coal_bits_for(dtype)};
+    return QSV_OK;
+}
+
+qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits) {
+    if (!ctx) return QSV_ERR_ARG;
+    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+    std::string err;
+    TileConfig cfg{};
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return fail(ctx, s, err);
+    (dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64) = cfg;
     return QSV_OK;
 }
 
 qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int tile_bits,
-                            int low_bits, int64_t* npasses, int32_t* pass_of_gate,
+                            int low_bits, int reg_bits, int64_t* npasses, int32_t* pass_of_gate,
                             int32_t* exec_order, uint64_t* pass_qubits) {
     if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
     if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
     if (ng < 0 || (ng > 0 && (!g || !pass_of_gate || !exec_order || !pass_qubits)) || !npasses)
         return QSV_ERR_ARG;
-    const int kmax = tile_bits_max(dtype);
-    const int tb = tile_bits ? tile_bits : kDefaultTileBits;
-    const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    if (tb < kMinTileBits || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
+    std::string err;
+    TileConfig cfg{};
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return s;
     // positions only: rotations get a placeholder angle
     std::vector<double> zeros(size_t(ng) + 1, 0.0);
     std::vector<qsv_gate> gg(g, g + ng);
@@ -650,7 +676,7 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
         if (x.kind == QSV_GROT) x.param = 0;
     std::vector<PGate> pg;
     if (qsv_status s = lower(nullptr, n, gg.data(), ng, zeros.data(), 1, pg)) return s;
-    std::vector<Pass> passes = plan_passes(n, pg, TileConfig{tb, lb});
+    std::vector<Pass> passes = plan_passes(n, pg, cfg);
     int64_t k = 0;
     for (size_t p = 0; p < passes.size(); ++p) {
         uint64_t qm = 0;
@@ -669,19 +695,18 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
 }
 
 qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
-                          int64_t nparams, int tile_bits, int low_bits, qsv_gate* out, int64_t cap,
-                          int32_t* pass_of_out, int64_t* nout) {
+                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, qsv_gate* out,
+                          int64_t cap, int32_t* pass_of_out, int64_t* nout) {
     if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
     if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
     if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
-    const int kmax = tile_bits_max(dtype);
-    const int tb = tile_bits ? tile_bits : kDefaultTileBits;
-    const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    if (tb < kMinTileBits || tb > kmax || lb < 0 || lb > tb - 2) return QSV_ERR_ARG;
+    std::string err;
+    TileConfig cfg{};
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return s;
     std::vector<PGate> pg;
     if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
     if (n >= kMinTileBits) pg = prefuse(pg);
-    std::vector<Pass> passes = plan_passes(n, pg, TileConfig{tb, lb});
+    std::vector<Pass> passes = plan_passes(n, pg, cfg);
     int64_t k = 0;
     auto emit = [&](const PGate& x, int32_t p) {
         if (k < cap) {
@@ -701,9 +726,18 @@ qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const
         const Pass& ps = passes[p];
         if (ps.single || ps.stages.empty()) {
             for (int gi : ps.gates) emit(pg[size_t(gi)], int32_t(p));
+            logf("plan: pass %zu single gate", p);
         } else {
-            for (const Stage& st : ps.stages)
-                for (const PGate& x : fuse_stage(pg, st.gates)) emit(x, int32_t(p));
+            std::string st_desc;
+            size_t nf = 0;
+            for (const Stage& st : ps.stages) {
+                const std::vector<PGate> f = fuse_stage(pg, st.gates);
+                for (const PGate& x : f) emit(x, int32_t(p));
+                nf += f.size();
+                st_desc += " " + std::to_string(f.size());
+            }
+            logf("plan: pass %zu: %zu gates -> %zu fused, %zu stages (fused gates per stage:%s)", p,
+                 ps.gates.size(), nf, ps.stages.size(), st_desc.c_str());
         }
     }
     *nout = k;

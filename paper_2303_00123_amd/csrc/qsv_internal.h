@@ -33,10 +33,12 @@ struct PGate {
 constexpr int KROT = 16;
 inline bool is_1q(int kind) { return kind == QSV_G1Q || kind == KROT; }
 
+inline int coal_bits_for(int dtype) { return dtype == QSV_C128 ? 3 : 4; }
+
 // A stage of a tile pass: the gates applied while each thread holds the
 // amplitudes spanning `rbits` (local tile bits) in registers.
 struct Stage {
-    int nr = 0;                  // register bits used by this pass's kernel (= tile bits - 8)
+    int nr = 0;                  // register bits of the pass's kernel
     int rbits[8] = {0};          // register bit j <-> local tile bit rbits[j]
     std::vector<int> gates;      // indices into the lowered gate list, in execution order
 };
@@ -45,6 +47,8 @@ struct Stage {
 struct Pass {
     bool single = false;         // true: one gate, unfused kernel
     int k = 0;                   // tile bits (tile = 2^k amplitudes)
+    int rb = 0;                  // register bits per thread (2^(k - rb) threads)
+    int coal = 0;                // local bits the first/last stage keep on lanes
     int pos[24] = {0};           // ascending global bit positions of the tile's local bits
     std::vector<int> gates;      // indices into the lowered gate list, in execution order
     std::vector<Stage> stages;   // stage 0 and the last stage use the canonical mapping
@@ -53,11 +57,18 @@ struct Pass {
 struct TileConfig {
     int tile_bits;   // log2 amplitudes per tile
     int low_bits;    // contiguous low bits kept in every tile
+    int reg_bits;    // log2 amplitudes per thread (threads per tile = 2^(tile_bits - reg_bits))
+    int coal_bits;   // the first and last stage keep local bits [0, coal_bits) on lanes, so
+                     // global loads and stores move 2^coal_bits contiguous amplitudes per lane group
 };
 
-constexpr int kTileThreads = 256;   // threads per tile workgroup (8 thread bits)
+constexpr int kTileThreads = 256;   // threads per workgroup of the batch and adjoint kernels
 constexpr int kMinTileBits = 10;    // at least 2 register bits per thread
 constexpr int kDefaultTileBits = 12;
+constexpr int kDefaultRegBits = 4;
+
+// (tile_bits, reg_bits) pairs the single-state tile kernel is compiled for
+bool tile_shape_supported(int dtype, int tile_bits, int reg_bits);
 
 // Group gates into passes (greedy, dependency-respecting), then split each
 // tile pass into register stages.
@@ -97,7 +108,7 @@ struct TGate {
 // Stage record in device memory.
 struct TStage {
     int32_t gbeg, gend;     // gate range [gbeg, gend) of the pass's gate array
-    int32_t tbits[8];       // thread-id bit j <-> local bit
+    int32_t tbits[10];      // thread-id bit j <-> local bit
     uint32_t su[32];        // byte offset (after the LDS swizzle) of register slot u
 };
 
@@ -107,16 +118,21 @@ struct TPassHdr {
     int32_t k;
     int32_t nstages;
     int32_t ngates;
-    int32_t pad;
+    int32_t pad;            // adjoint passes: number of rotation partial-sum slots
+    int32_t rb;             // register bits
+    int32_t pad2;
     int32_t pos[24];
+    int32_t tpos_ld[10];    // global position of thread-id bit j in the load mapping
+    int32_t tpos_st[10];    // ... in the store mapping
     uint64_t du[32];        // amplitude offset of register slot u in the load mapping
+    uint64_t du_st[32];     // ... in the store mapping
 };
 
 // LDS slot swizzle of the tile kernels: an XOR of the slot index with a fold
 // of its higher bits into the bank-selecting low bits.  It is linear over
 // GF(2), so swz(a | b) = swz(a) ^ swz(b) for disjoint a, b.
 __host__ __device__ inline uint32_t tile_swz(uint32_t e, int elem_bytes) {
-    return elem_bytes == 16 ? e ^ (((e >> 4) ^ (e >> 8)) & 15u)
+    return elem_bytes == 16 ? e ^ (((e >> 4) ^ (e >> 8) ^ (e >> 12)) & 15u)
                             : e ^ (((e >> 5) ^ (e >> 10)) & 31u);
 }
 
@@ -148,8 +164,8 @@ struct qsv_ctx_s {
     double* d_aux = nullptr;
     size_t d_aux_doubles = 0;
 
-    qsv::TileConfig tile_c128{12, 3};
-    qsv::TileConfig tile_c64{12, 4};
+    qsv::TileConfig tile_c128{12, 3, 4, 3};
+    qsv::TileConfig tile_c64{12, 4, 4, 4};
 
     // profiling
     bool profiling = false;
@@ -198,6 +214,11 @@ void prof_before(qsv_ctx ctx, const char* name, double bytes);
 void prof_after(qsv_ctx ctx);
 void prof_before_on(qsv_ctx ctx, hipStream_t stream, const char* name, double bytes);
 void prof_after_on(qsv_ctx ctx, hipStream_t stream);
+
+// Diagnostics to stderr when the environment variable QSV_LOG is set to a
+// non-zero value (planner decisions, launch shapes, host planning time).
+bool log_enabled();
+void logf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 // exp(-i theta P / 2) for Pauli `axis`, as a 2x2 row-major (re, im) matrix
 void rotation_matrix(int axis, double theta, double* m);

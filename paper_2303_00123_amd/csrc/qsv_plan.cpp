@@ -62,7 +62,8 @@ static void greedy(const std::vector<int>& rem, const std::vector<uint64_t>& mas
 static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     (void)n;
     const int K = ps.k;
-    const int RB = K - 8;
+    const int RB = ps.rb;
+    const int C = std::min(ps.coal, K - RB);
     int loc[64];
     for (int p = 0; p < 64; ++p) loc[p] = -1;
     for (int b = 0; b < K; ++b) loc[ps.pos[b]] = b;
@@ -74,55 +75,64 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         if (!is_1q(g.kind)) m |= uint64_t(1) << loc[g.p1];
         lm[size_t(gi)] = m;
     }
-    const uint64_t canon = ((uint64_t(1) << K) - 1) & ~uint64_t(0xFF);   // local bits 8..K-1
-    auto make_stage = [&](uint64_t S, std::vector<int>&& g) {
+    const uint64_t lanes = (uint64_t(1) << C) - 1;   // bits the first/last stage keep on lanes
+    // a register set of RB bits containing S; padding prefers the highest free
+    // bits, and never the lane bits when `avoid` is set
+    auto make_stage = [&](uint64_t S, bool avoid, std::vector<int>&& g) {
         Stage st;
         st.nr = RB;
+        for (int b = K - 1; b >= 0 && __builtin_popcountll(S) < RB; --b)
+            if (!((S >> b) & 1) && !(avoid && ((lanes >> b) & 1))) S |= uint64_t(1) << b;
         int j = 0;
         for (int b = 0; b < K && j < RB; ++b)
             if ((S >> b) & 1) st.rbits[j++] = b;
-        // pad with the highest unused local bits
-        for (int b = K - 1; b >= 0 && j < RB; --b)
-            if (!((S >> b) & 1)) {
-                S |= uint64_t(1) << b;
-                st.rbits[j++] = b;
-            }
-        std::sort(st.rbits, st.rbits + RB);
         st.gates = std::move(g);
         return st;
     };
+    // greedy scan that may not use the lane bits (first stage)
+    auto greedy_avoid = [&](const std::vector<int>& rem, uint64_t& S, std::vector<int>& take,
+                            std::vector<int>& defer) {
+        uint64_t blocked = 0;
+        for (int gi : rem) {
+            const uint64_t gm = lm[size_t(gi)];
+            if ((gm & blocked) || (gm & lanes)) {
+                defer.push_back(gi);
+                blocked |= gm;
+                continue;
+            }
+            const uint64_t need = gm & ~S;
+            if (__builtin_popcountll(S | need) <= RB) {
+                S |= need;
+                take.push_back(gi);
+            } else {
+                defer.push_back(gi);
+                blocked |= gm;
+            }
+        }
+    };
 
-    std::vector<int> rem = ps.gates, take, defer;
-    uint64_t S = canon;
-    greedy(rem, lm, S, RB, true, take, defer);
     ps.stages.clear();
-    ps.stages.push_back(make_stage(canon, std::move(take)));
+    std::vector<int> rem = ps.gates, take, defer;
+    uint64_t S = 0;
+    greedy_avoid(rem, S, take, defer);
+    ps.stages.push_back(make_stage(S, true, std::move(take)));
     rem.swap(defer);
-    std::vector<Stage> middle;
     while (!rem.empty()) {
         take.clear();
         defer.clear();
         S = 0;
         greedy(rem, lm, S, RB, false, take, defer);
-        middle.push_back(make_stage(S, std::move(take)));
+        uint64_t used = 0;
+        for (int gi : take) used |= lm[size_t(gi)];
+        // a stage that avoids the lane bits can also be the store stage
+        ps.stages.push_back(make_stage(S, (used & lanes) == 0, std::move(take)));
         rem.swap(defer);
     }
-    if (middle.empty()) return;   // single stage: load, apply, store
-    // the last middle stage becomes the canonical store stage if it fits
-    Stage last;
-    last.nr = RB;
-    for (int j = 0; j < RB; ++j) last.rbits[j] = 8 + j;
-    const Stage& lm_st = middle.back();
-    uint64_t used = 0;
-    for (int gi : lm_st.gates) used |= lm[size_t(gi)];
-    if ((used & ~canon) == 0) {
-        last.gates = lm_st.gates;
-        middle.pop_back();
-    }
-    for (auto& m : middle) ps.stages.push_back(std::move(m));
-    ps.stages.push_back(std::move(last));
+    // the store needs a stage that keeps the lane bits on lanes
+    uint64_t lastreg = 0;
+    for (int j = 0; j < ps.stages.back().nr; ++j) lastreg |= uint64_t(1) << ps.stages.back().rbits[j];
+    if (lastreg & lanes) ps.stages.push_back(make_stage(0, true, {}));
 }
-
 
 // ------------------------------------------------------------ stage fusion
 namespace {
@@ -333,6 +343,8 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
         Pass ps;
         ps.single = (take.size() == 1);
         ps.k = K;
+        ps.rb = tile_shape_supported(QSV_C128, K, cfg.reg_bits) ? cfg.reg_bits : K - 8;
+        ps.coal = cfg.coal_bits;
         int i = 0;
         for (int p = 0; p < n; ++p)
             if ((S >> p) & 1) ps.pos[i++] = p;

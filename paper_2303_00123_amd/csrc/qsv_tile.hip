@@ -27,14 +27,13 @@ using namespace tile;
 // One workgroup per tile.  Every stage record (including the first and the
 // last, which carry the load mapping) drives the same loop body, so the gate
 // dispatch is compiled once.  Slot offsets come precomputed in the plan.
-template <typename R, int K>
-__global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __restrict__ s,
-                                                   const char* __restrict__ plan) {
+template <typename R, int K, int RB>
+__global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* __restrict__ s,
+                                                        const char* __restrict__ plan) {
     using V = typename V2T<R>::type;
     constexpr int E = 1 << K;
-    constexpr int RB = K - 8;
+    constexpr int TB = K - RB;
     constexpr int P = 1 << RB;
-    constexpr uint32_t ES = sizeof(V);   // bytes per LDS slot
     __shared__ V tile[E];
     char* lds = reinterpret_cast<char*>(tile);
 
@@ -50,15 +49,15 @@ __global__ __launch_bounds__(kThreads) void k_tile(typename V2T<R>::type* __rest
     uint64_t b = blockIdx.x;
 #pragma unroll
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
-    V* const sp = s + (b | deposit(tid, hdr->pos, 8));
+    V* const sp = s + (b | deposit(tid, hdr->tpos_ld, TB));
 
     V v[P];
 #pragma unroll
     for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
-
-    run_stages<R, K>(v, lds, stg, nst, gates, tid);
+    run_stages<R, K, RB>(v, lds, stg, nst, gates, tid);
+    V* const sq = s + (b | deposit(tid, hdr->tpos_st, TB));
 #pragma unroll
-    for (int u = 0; u < P; ++u) sp[hdr->du[u]] = v[u];
+    for (int u = 0; u < P; ++u) sq[hdr->du_st[u]] = v[u];
 }
 
 // ------------------------------------------------------------ host side
@@ -141,24 +140,27 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
     return true;
 }
 
-template <typename R, int K>
+template <typename R, int K, int RB>
 hipError_t launch_tile(qsv_ctx ctx, void* s, int n, const char* dplan) {
     using V = typename V2T<R>::type;
     const unsigned tiles = unsigned(uint64_t(1) << (n - K));
-    hipLaunchKernelGGL((k_tile<R, K>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
+    hipLaunchKernelGGL((k_tile<R, K, RB>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
                        static_cast<V*>(s), dplan);
     return hipGetLastError();
 }
 
+// The compiled (tile bits, register bits) shapes: 256 threads for every
+// tile size, plus 512-thread variants (more waves per SIMD) at 2^12 and 2^13
+// and 2^13-amplitude tiles with 32 amplitudes per thread.
 template <typename R>
-hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, const char* dplan) {
-    switch (k) {
-    case 10: return launch_tile<R, 10>(ctx, s, n, dplan);
-    case 11: return launch_tile<R, 11>(ctx, s, n, dplan);
-    case 12: return launch_tile<R, 12>(ctx, s, n, dplan);
-    case 13:
-        if constexpr (TileK<R>::value >= 13) return launch_tile<R, 13>(ctx, s, n, dplan);
-        return hipErrorInvalidValue;
+hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, const char* dplan) {
+    switch (k * 8 + rb) {
+    case 10 * 8 + 2: return launch_tile<R, 10, 2>(ctx, s, n, dplan);
+    case 11 * 8 + 3: return launch_tile<R, 11, 3>(ctx, s, n, dplan);
+    case 12 * 8 + 3: return launch_tile<R, 12, 3>(ctx, s, n, dplan);
+    case 12 * 8 + 4: return launch_tile<R, 12, 4>(ctx, s, n, dplan);
+    case 13 * 8 + 4: return launch_tile<R, 13, 4>(ctx, s, n, dplan);
+    case 13 * 8 + 5: return launch_tile<R, 13, 5>(ctx, s, n, dplan);
     default: return hipErrorInvalidValue;
     }
 }
@@ -183,14 +185,29 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
     for (int p = 0; p < 64; ++p) loc[p] = -1;
     for (int b = 0; b < 24; ++b) hd->pos[b] = b < ps.k ? ps.pos[b] : 0;
     for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
-    const int rb = ps.k - 8;
-    for (int u = 0; u < 32; ++u) {
-        uint64_t off = 0;
-        if (u < (1 << rb))
-            for (int j = 0; j < rb; ++j)
-                if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[8 + j];
-        hd->du[u] = off;
-    }
+    const int rb = ps.rb;
+    hd->rb = rb;
+    hd->pad2 = 0;
+    if (ps.stages.empty()) return false;
+    // load mapping = first stage's, store mapping = last stage's: thread bits
+    // are the complement of the register bits, ascending
+    auto mapping = [&](const Stage& st, int32_t* tpos, uint64_t* du) {
+        uint32_t used = 0;
+        for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
+        int tj = 0;
+        for (int b = 0; b < ps.k && tj < 10; ++b)
+            if (!((used >> b) & 1)) tpos[tj++] = ps.pos[b];
+        for (; tj < 10; ++tj) tpos[tj] = 0;
+        for (int u = 0; u < 32; ++u) {
+            uint64_t off = 0;
+            if (u < (1 << rb))
+                for (int j = 0; j < rb; ++j)
+                    if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[st.rbits[j]];
+            du[u] = off;
+        }
+    };
+    mapping(ps.stages.front(), hd->tpos_ld, hd->du);
+    mapping(ps.stages.back(), hd->tpos_st, hd->du_st);
     TStage* ts = reinterpret_cast<TStage*>(h + sizeof(TPassHdr));
     TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + sizeof(TPassHdr) + ps.stages.size() * sizeof(TStage));
     int gi = 0;
@@ -200,9 +217,9 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
         uint32_t used = 0;
         for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
         int tj = 0;
-        for (int b = 0; b < ps.k && tj < 8; ++b)
+        for (int b = 0; b < ps.k && tj < 10; ++b)
             if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
-        for (; tj < 8; ++tj) ts[si].tbits[tj] = 0;
+        for (; tj < 10; ++tj) ts[si].tbits[tj] = 0;
         for (int u = 0; u < 32; ++u) {
             uint32_t e = 0;
             if (u < (1 << st.nr))
@@ -255,7 +272,7 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
             e = launch_gate(ctx, s, n, dt, gates[size_t(ps.gates[0])]);
         } else {
             prof_before(ctx, pname, 2.0 * double(uint64_t(1) << n) * sizeof(V));
-            e = launch_tile_k<R>(ctx, s, n, ps.k, dev + offs[i]);
+            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, dev + offs[i]);
             prof_after(ctx);
         }
         if (e != hipSuccess) return e;
@@ -272,6 +289,15 @@ size_t pass_record_bytes(int dtype, const Pass& ps) {
 bool write_pass_record(int dtype, char* dst, const std::vector<PGate>& gates, const Pass& ps) {
     return dtype == QSV_C128 ? write_record_t<double>(dst, gates, ps)
                              : write_record_t<float>(dst, gates, ps);
+}
+
+bool tile_shape_supported(int dtype, int tile_bits, int reg_bits) {
+    (void)dtype;
+    switch (tile_bits * 8 + reg_bits) {
+    case 10 * 8 + 2: case 11 * 8 + 3: case 12 * 8 + 3: case 12 * 8 + 4: case 13 * 8 + 4:
+    case 13 * 8 + 5: return true;
+    default: return false;
+    }
 }
 
 int tile_bits_max(int dtype) { return dtype == QSV_C128 ? TileK<double>::value : TileK<float>::value; }

@@ -17,7 +17,7 @@ constexpr int kThreads = kTileThreads;
 template <typename R>
 struct TileK;
 template <>
-struct TileK<double> { static constexpr int value = 12; };   // 4096 x 16 B = 64 KiB
+struct TileK<double> { static constexpr int value = 13; };   // 8192 x 16 B = 128 KiB
 template <>
 struct TileK<float> { static constexpr int value = 13; };    // 8192 x 8 B = 64 KiB
 
@@ -129,7 +129,8 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
     case 2: if constexpr (RB > 2) f(IC<2>{}); break;
     case 3: if constexpr (RB > 3) f(IC<3>{}); break;
     case 4: if constexpr (RB > 4) f(IC<4>{}); break;
-    default: if constexpr (RB > 5) f(IC<5>{}); break;
+    case 5: if constexpr (RB > 5) f(IC<5>{}); break;
+    default: break;
     }
 }
 
@@ -175,16 +176,16 @@ __device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restric
 // the last stage use the load mapping; stages in between re-map through LDS.
 // Ends with every thread done reading LDS if the pass used it (the caller
 // may reuse `lds` right away only after its own barrier).
-template <typename R, int K, typename V>
-__device__ __forceinline__ void run_stages(V (&v)[1 << (K - 8)], char* lds, const TStage* stg,
+template <typename R, int K, int RB, typename V>
+__device__ __forceinline__ void run_stages(V (&v)[1 << RB], char* lds, const TStage* stg,
                                            int nst, const TGate<R>* gates, uint32_t tid) {
-    constexpr int RB = K - 8;
+    constexpr int TB = K - RB;
     constexpr int P = 1 << RB;
     constexpr uint32_t ES = sizeof(V);
     for (int st = 0; st < nst; ++st) {
         const TStage& S = stg[st];
         // LDS byte address of slot u = swz(eb | du) * ES = swz(eb) * ES ^ su[u]
-        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
+        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, TB)) * ES;
         if (st > 0) {
 #pragma unroll
             for (int u = 0; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sb ^ S.su[u]));

@@ -1,6 +1,8 @@
 // Autotuner cache for batch tile shapes: an in-context map from batch shape
 // key to (tile_bits, low_bits), optionally persisted as one JSON object per
 // line in the file named by QSV_TUNE_CACHE, keyed by GPU architecture.
+#include <chrono>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -9,6 +11,24 @@
 #include "qsv_internal.h"
 
 namespace qsv {
+
+bool log_enabled() {
+    static const int on = [] {
+        const char* v = std::getenv("QSV_LOG");
+        return (v && *v && std::strcmp(v, "0") != 0) ? 1 : 0;
+    }();
+    return on != 0;
+}
+
+void logf(const char* fmt, ...) {
+    if (!log_enabled()) return;
+    std::va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[qsv] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    va_end(ap);
+}
 
 static std::string arch_name(qsv_ctx ctx) {
     hipDeviceProp_t p{};

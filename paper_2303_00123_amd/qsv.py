@@ -94,9 +94,9 @@ def lib():
         "qsv_batch_run": [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, i32, vp, i32],
         "qsv_profile_begin": [vp],
         "qsv_profile_end": [vp, vp, i32, P(i32)],
-        "qsv_set_tile": [vp, i32, i32, i32],
-        "qsv_plan_circuit": [i32, i32, vp, i64, i32, i32, P(i64), vp, vp, vp],
-        "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, vp, i64, vp, P(i64)],
+        "qsv_set_tile": [vp, i32, i32, i32, i32],
+        "qsv_plan_circuit": [i32, i32, vp, i64, i32, i32, i32, P(i64), vp, vp, vp],
+        "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, i32, vp, i64, vp, P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -179,8 +179,8 @@ class Context:
     def sync(self):
         self.check(lib().qsv_sync(self.handle))
 
-    def set_tile(self, dtype: int, tile_bits: int = 0, low_bits: int = 0):
-        self.check(lib().qsv_set_tile(self.handle, dtype, tile_bits, low_bits))
+    def set_tile(self, dtype: int, tile_bits: int = 0, low_bits: int = 0, reg_bits: int = 0):
+        self.check(lib().qsv_set_tile(self.handle, dtype, tile_bits, low_bits, reg_bits))
 
     def profile_begin(self):
         self.check(lib().qsv_profile_begin(self.handle))
@@ -195,35 +195,16 @@ class Context:
                                          "bytes": float(arr[k].bytes)}
         return out
 
-    def batch_run(self, circuits: Sequence, dtype: int, flags: int = 0) -> np.ndarray:
-        """Run circuits (objects with n, gates, params, observable) in one
-        persistent launch; returns out[b] = <O_b> per circuit."""
-        nb = len(circuits)
-        nq = np.array([c.n for c in circuits], dtype=np.int32)
-        gates, params, masks, ws = [], [], [], []
-        goff, toff = [0], [0]
-        for c in circuits:
-            g = marshal_gates(c.gates)
-            pbase = sum(len(p) for p in params)
-            rot = g["kind"] == GROT
-            g["param"][rot] += pbase
-            gates.append(g)
-            params.append(np.asarray(c.params, dtype=np.float64))
-            m, w = observable_arrays(c.observable)
-            masks.append(m)
-            ws.append(w)
-            goff.append(goff[-1] + len(g))
-            toff.append(toff[-1] + len(w))
-        g = np.concatenate(gates) if gates else np.zeros(0, dtype=GATE_DTYPE)
-        p = np.concatenate(params) if params else np.zeros(0)
-        m = np.concatenate(masks).astype(np.uint64)
-        w = np.concatenate(ws)
-        goff = np.asarray(goff, dtype=np.int64)
-        toff = np.asarray(toff, dtype=np.int64)
-        out = np.zeros(nb, dtype=np.float64)
-        self.check(lib().qsv_batch_run(self.handle, nb, _ptr(nq), _ptr(goff), _ptr(g), _ptr(p),
-                                       p.size, _ptr(toff), _ptr(m), _ptr(w), dtype, _ptr(out),
-                                       flags))
+    def batch_run(self, circuits, dtype: int, flags: int = 0, params=None) -> np.ndarray:
+        """Run a batch (a BatchSpec, or a sequence of circuit objects with n,
+        gates, params, observable) in one persistent launch; returns
+        out[b] = <O_b>.  `params` replaces the spec's concatenated angles."""
+        spec = circuits if isinstance(circuits, BatchSpec) else BatchSpec(circuits)
+        p = spec.params if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        out = np.zeros(spec.nb, dtype=np.float64)
+        self.check(lib().qsv_batch_run(self.handle, spec.nb, _ptr(spec.nq), _ptr(spec.goff),
+                                       _ptr(spec.gates), _ptr(p), p.size, _ptr(spec.toff),
+                                       _ptr(spec.masks), _ptr(spec.w), dtype, _ptr(out), flags))
         return out
 
     def close(self):
@@ -236,6 +217,38 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class BatchSpec:
+    """Marshalled form of a batch of circuits for qsv_batch_run: qubit
+    counts, gate records and offsets, concatenated angles (rotation indices
+    rebased onto them), observable terms and offsets."""
+
+    def __init__(self, circuits: Sequence):
+        self.nb = len(circuits)
+        self.nq = np.array([c.n for c in circuits], dtype=np.int32)
+        gates, params, masks, ws = [], [], [], []
+        goff, toff = [0], [0]
+        pbase = 0
+        for c in circuits:
+            g = marshal_gates(c.gates)
+            rot = g["kind"] == GROT
+            g["param"][rot] += pbase
+            p = np.asarray(c.params, dtype=np.float64)
+            pbase += p.size
+            gates.append(g)
+            params.append(p)
+            m, w = observable_arrays(c.observable)
+            masks.append(m)
+            ws.append(w)
+            goff.append(goff[-1] + len(g))
+            toff.append(toff[-1] + len(w))
+        self.gates = np.concatenate(gates) if gates else np.zeros(0, dtype=GATE_DTYPE)
+        self.params = np.concatenate(params) if params else np.zeros(0)
+        self.masks = np.concatenate(masks).astype(np.uint64)
+        self.w = np.concatenate(ws)
+        self.goff = np.asarray(goff, dtype=np.int64)
+        self.toff = np.asarray(toff, dtype=np.int64)
 
 
 class State:
@@ -332,7 +345,8 @@ class State:
             pass
 
 
-def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_bits: int = 0):
+def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_bits: int = 0,
+                 reg_bits: int = 0):
     """Host-only fusion plan: (pass_of_gate, exec_order, pass_qubit_masks)."""
     g = marshal_gates(gates)
     ng = len(g)
@@ -340,7 +354,7 @@ def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_b
     order = np.zeros(max(ng, 1), dtype=np.int32)
     pq = np.zeros(max(ng, 1), dtype=np.uint64)
     npass = ctypes.c_int64()
-    st = lib().qsv_plan_circuit(n, dtype, _ptr(g), ng, tile_bits, low_bits, ctypes.byref(npass),
+    st = lib().qsv_plan_circuit(n, dtype, _ptr(g), ng, tile_bits, low_bits, reg_bits, ctypes.byref(npass),
                                 _ptr(pog), _ptr(order), _ptr(pq))
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_circuit failed")
@@ -348,7 +362,7 @@ def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_b
 
 
 def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int = 0,
-               low_bits: int = 0):
+               low_bits: int = 0, reg_bits: int = 0):
     """Host-only: the exact gate records the kernels apply, in order, and the
     pass index of each (see qsv_plan_fused)."""
     g = marshal_gates(gates)
@@ -358,7 +372,7 @@ def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int
     pas = np.zeros(cap, dtype=np.int32)
     nout = ctypes.c_int64()
     st = lib().qsv_plan_fused(n, dtype, _ptr(g), len(g), _ptr(p), p.size, tile_bits, low_bits,
-                              _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
+                              reg_bits, _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_fused failed")
     return out[: nout.value], pas[: nout.value]

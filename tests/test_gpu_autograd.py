@@ -1,0 +1,93 @@
+"""torch.autograd wrapper of the adjoint sweep: values and gradients against
+the FP64 oracle (adjoint method and parameter shift), repeated and
+interleaved calls, and an optimiser step."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no HIP device")
+    return t
+
+
+@pytest.fixture(scope="module")
+def AG(torch):
+    from paper_2303_00123_amd import autograd
+    return autograd
+
+
+def wsum(c):
+    return max(1.0, sum(abs(w) for _, w in c.observable))
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.hea_cz_ring(12, 3, seed=21),
+    lambda: W.ry_rz_cnot_ladder(13, 3, np.random.default_rng(22)),
+])
+def test_value_and_grad_match_oracle(torch, AG, maker):
+    c = maker()
+    ev = AG.Expectation(c.n, c.gates, c.observable)
+    th = torch.tensor(c.params, dtype=torch.float64, requires_grad=True)
+    f = ev(th)
+    f.backward()
+    f_ref, g_ref = O.adjoint(c)
+    assert abs(f.item() - f_ref) <= 1e-12 * wsum(c)
+    assert np.max(np.abs(th.grad.numpy() - g_ref)) <= 1e-10 * wsum(c)
+    sel = list(range(0, len(c.params), 5))
+    assert np.max(np.abs(th.grad.numpy()[sel] - O.param_shift(c, sel))) <= 1e-10 * wsum(c)
+
+
+def test_interleaved_calls_recompute_the_state(torch, AG):
+    """Two forwards, then the backward of the first: its state was
+    overwritten by the second call and must be recomputed from its angles."""
+    c = W.hea_cz_ring(11, 2, seed=23)
+    ev = AG.Expectation(c.n, c.gates, c.observable)
+    rng = np.random.default_rng(24)
+    p1 = c.params.copy()
+    p2 = rng.uniform(0, 2 * np.pi, size=p1.size)
+    t1 = torch.tensor(p1, requires_grad=True)
+    t2 = torch.tensor(p2, requires_grad=True)
+    f1 = ev(t1)
+    f2 = ev(t2)
+    (3.0 * f1).backward()
+    f2.backward()
+    c1, c2 = W.Circuit(c.n, c.gates, p1, c.observable), W.Circuit(c.n, c.gates, p2, c.observable)
+    r1, g1 = O.adjoint(c1)
+    r2, g2 = O.adjoint(c2)
+    tol = 1e-10 * wsum(c)
+    assert abs(f1.item() - r1) <= tol and abs(f2.item() - r2) <= tol
+    assert np.max(np.abs(t1.grad.numpy() - 3.0 * g1)) <= 3 * tol
+    assert np.max(np.abs(t2.grad.numpy() - g2)) <= tol
+    # a second backward through a retained graph recomputes as well
+    t3 = torch.tensor(p1, requires_grad=True)
+    f3 = ev(t3)
+    f3.backward(retain_graph=True)
+    f3.backward()
+    assert np.max(np.abs(t3.grad.numpy() - 2.0 * g1)) <= 2 * tol
+
+
+def test_optimiser_step_lowers_energy(torch, AG):
+    c = W.hea_cz_ring(10, 2, seed=25)
+    ev = AG.Expectation(c.n, c.gates, c.observable)
+    th = torch.tensor(c.params, requires_grad=True)
+    opt = torch.optim.SGD([th], lr=0.05)
+    e0 = None
+    for _ in range(5):
+        opt.zero_grad()
+        f = ev(th)
+        if e0 is None:
+            e0 = f.item()
+        f.backward()
+        opt.step()
+    assert ev(th.detach()).item() < e0
+    # the oracle agrees with the final value
+    cf = W.Circuit(c.n, c.gates, th.detach().numpy().copy(), c.observable)
+    assert abs(ev(th.detach()).item() - O.energy(cf)) <= 1e-12 * wsum(c)

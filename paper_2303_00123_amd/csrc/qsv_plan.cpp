@@ -59,6 +59,65 @@ static void greedy(const std::vector<int>& rem, const std::vector<uint64_t>& mas
     }
 }
 
+// Number of gates of `rem` (circuit order) that a pass over the fixed bit
+// set S takes under the blocking rule; the scan stops once every bit of S is
+// blocked, since no later gate can join then.
+static size_t closure_count(const std::vector<int>& rem, size_t lim, const std::vector<uint64_t>& masks,
+                            uint64_t S) {
+    uint64_t blocked = 0;
+    size_t cnt = 0;
+    for (size_t j = 0; j < lim; ++j) {
+        const uint64_t gm = masks[size_t(rem[j])];
+        if (!(gm & ~S) && !(gm & blocked)) {
+            ++cnt;
+        } else {
+            blocked |= gm;
+            if ((blocked & S) == S) break;
+        }
+    }
+    return cnt;
+}
+
+// Bit set of the next pass: start from the low bits and repeatedly add the
+// bits of one not-yet-blocked gate, choosing the addition after which the
+// pass takes the most gates (ties: fewer new bits, then circuit order),
+// until no gate's bits fit in the K positions.  This looks past the first
+// gates in circuit order, which an in-order greedy fill would commit to.
+static uint64_t choose_bits(const std::vector<int>& rem, const std::vector<uint64_t>& masks, uint64_t S, int K) {
+    const size_t lim = std::min(rem.size(), size_t(4096));
+    for (;;) {
+        const int have = __builtin_popcountll(S);
+        if (have >= K) break;
+        uint64_t cand[64];
+        int nc = 0;
+        uint64_t blocked = 0;
+        for (size_t j = 0; j < lim && nc < 64; ++j) {
+            const uint64_t gm = masks[size_t(rem[j])];
+            const uint64_t need = gm & ~S;
+            if (need && !(gm & blocked) && have + __builtin_popcountll(need) <= K) {
+                bool dup = false;
+                for (int c = 0; c < nc; ++c) dup |= cand[c] == need;
+                if (!dup) cand[nc++] = need;
+            }
+            if (need || (gm & blocked)) blocked |= gm;
+            if (__builtin_popcountll(blocked & ~S) + have >= 64) break;
+        }
+        if (nc == 0) break;
+        size_t best_cnt = 0;
+        int best = -1;
+        for (int c = 0; c < nc; ++c) {
+            const size_t cnt = closure_count(rem, lim, masks, S | cand[c]);
+            if (best < 0 || cnt > best_cnt ||
+                (cnt == best_cnt && __builtin_popcountll(cand[c]) < __builtin_popcountll(cand[best]))) {
+                best = c;
+                best_cnt = cnt;
+            }
+        }
+        S |= cand[best];
+    }
+    return S;
+}
+
 static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     (void)n;
     const int K = ps.k;
@@ -205,6 +264,27 @@ M4 as4(const PGate& g) {
 
 }  // namespace
 
+// Arithmetic cost of a gate in real FMAs per amplitude, as the tile kernel
+// applies it: dense 1q 8, diagonal 1q 4, controlled 1q 4 (half the
+// amplitudes), controlled X 0 (a register swap), controlled diagonal 2,
+// dense 2q 16 (a control on state 0 is applied as a dense 2q).
+static bool offdiag_zero(const double* m) { return m[2] == 0.0 && m[3] == 0.0 && m[4] == 0.0 && m[5] == 0.0; }
+static bool is_pauli_x(const double* m) {
+    return m[0] == 0.0 && m[1] == 0.0 && m[2] == 1.0 && m[3] == 0.0 && m[4] == 1.0 && m[5] == 0.0 &&
+           m[6] == 0.0 && m[7] == 0.0;
+}
+static int gate_cost(const PGate& g) {
+    switch (g.kind) {
+    case QSV_G1Q: return offdiag_zero(g.m) ? 4 : 8;
+    case QSV_GC1Q:
+        if (g.cs == 0) return 16;
+        return is_pauli_x(g.m) ? 0 : offdiag_zero(g.m) ? 2 : 4;
+    case KROT: return 8;
+    default: return 16;
+    }
+}
+static int cost1(const cd* u) { return (u[1] == 0.0 && u[2] == 0.0) ? 4 : 8; }
+
 std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector<int>& idx) {
     std::vector<PGate> out;
     bool has[64] = {false};
@@ -213,22 +293,49 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
     int last[64];
     for (int p = 0; p < 64; ++p) last[p] = -1;
 
+    // emit the pending 1-qubit product on position p: folded into the last
+    // gate on p when that costs nothing (a 1q gate on p, or a dense 2q gate;
+    // no gate on p follows it, so left-multiplying it is exact), else as a
+    // gate of its own
+    auto flush = [&](int p) {
+        if (!has[p]) return;
+        has[p] = false;
+        const int l = last[p];
+        if (l >= 0 && out[size_t(l)].kind == QSV_G1Q) {
+            PGate& o = out[size_t(l)];
+            cd u[4];
+            m2_from(o.m, u);
+            m2_mul(pend[p], u, u);
+            for (int i = 0; i < 4; ++i) {
+                o.m[2 * i] = u[i].real();
+                o.m[2 * i + 1] = u[i].imag();
+            }
+            return;
+        }
+        if (l >= 0 && out[size_t(l)].kind == QSV_G2Q) {
+            PGate& o = out[size_t(l)];
+            static const cd I2[4] = {1, 0, 0, 1};
+            const M4 L = o.p0 == p ? kron(pend[p], I2) : kron(I2, pend[p]);
+            m4_to(mul(L, m4_from(o.m)), o.m);
+            return;
+        }
+        PGate f{};
+        f.kind = QSV_G1Q;
+        f.p0 = p;
+        f.cs = 1;
+        for (int i = 0; i < 4; ++i) {
+            f.m[2 * i] = pend[p][i].real();
+            f.m[2 * i + 1] = pend[p][i].imag();
+        }
+        out.push_back(f);
+        last[p] = int(out.size()) - 1;
+    };
+
     for (int gi : idx) {
         const PGate& g = gates[size_t(gi)];
         if (g.kind == KROT) {
-            // kept whole: flush a pending 1-qubit product on its qubit first
-            if (has[g.p0]) {
-                PGate f{};
-                f.kind = QSV_G1Q;
-                f.p0 = g.p0;
-                f.cs = 1;
-                for (int i = 0; i < 4; ++i) {
-                    f.m[2 * i] = pend[g.p0][i].real();
-                    f.m[2 * i + 1] = pend[g.p0][i].imag();
-                }
-                out.push_back(f);
-                has[g.p0] = false;
-            }
+            // kept whole (its partial sum is taken at this point)
+            flush(g.p0);
             out.push_back(g);
             last[g.p0] = int(out.size()) - 1;
             continue;
@@ -244,15 +351,22 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
             continue;
         }
         const int a = g.p0, b = g.p1;
-        const bool absorb = has[a] || has[b];
-        // merge with the previous gate if it is the last one on both positions
-        // and acts on exactly this pair
+        // the previous gate, if it is the last one on both positions and acts
+        // on exactly this pair (pending 1q gates on a, b lie between the two)
         int prev = -1;
         if (last[a] >= 0 && last[a] == last[b]) {
             const PGate& o = out[size_t(last[a])];
-            if (!is_1q(o.kind) && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a))) prev = last[a];
+            if (!is_1q(o.kind) && o.kind != KROT && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a)))
+                prev = last[a];
         }
-        if (!absorb && prev < 0) {
+        // fuse into one dense 2q gate only where that does not add arithmetic
+        const int pend_cost = (has[a] ? cost1(pend[a]) : 0) + (has[b] ? cost1(pend[b]) : 0);
+        const int own = gate_cost(g) + pend_cost;
+        bool merge_prev = prev >= 0 && 16 <= own + gate_cost(out[size_t(prev)]);
+        const bool absorb = (has[a] || has[b]) && (merge_prev || 16 <= own);
+        if (!absorb && !merge_prev) {
+            flush(a);
+            flush(b);
             out.push_back(g);
             last[a] = last[b] = int(out.size()) - 1;
             continue;
@@ -265,7 +379,7 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
             M = mul(M, kron(ua, ub));
             has[a] = has[b] = false;
         }
-        if (prev >= 0) {
+        if (merge_prev) {
             PGate& o = out[size_t(prev)];
             M4 P = as4(o);
             if (o.p0 != a) P = swapq(P);   // express the earlier gate in basis (a, b)
@@ -286,19 +400,7 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
             last[a] = last[b] = int(out.size()) - 1;
         }
     }
-    for (int p = 0; p < 64; ++p)
-        if (has[p]) {
-            PGate f{};
-            f.kind = QSV_G1Q;
-            f.p0 = p;
-            f.p1 = 0;
-            f.cs = 1;
-            for (int i = 0; i < 4; ++i) {
-                f.m[2 * i] = pend[p][i].real();
-                f.m[2 * i + 1] = pend[p][i].imag();
-            }
-            out.push_back(f);
-        }
+    for (int p = 0; p < 64; ++p) flush(p);
     return out;
 }
 
@@ -328,10 +430,10 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
 
     while (!rem.empty()) {
-        uint64_t S = (uint64_t(1) << L) - 1;
+        uint64_t S = choose_bits(rem, masks, (uint64_t(1) << L) - 1, K);
         std::vector<int> take, defer;
         take.reserve(rem.size());
-        greedy(rem, masks, S, K, false, take, defer);
+        greedy(rem, masks, S, K, true, take, defer);
         int cnt = __builtin_popcountll(S);
         // fill the tile up to K positions with the lowest unused ones
         for (int p = 0; p < n && cnt < K; ++p) {

@@ -119,24 +119,29 @@ __device__ __forceinline__ double rot_part(const V (&v)[P], const V (&l)[P]) {
     return acc;
 }
 
+// (dv, dl) = gate(sv, sl) on both vectors; a rotation also emits its
+// partial Im<lam|P|psi> (taken before the rotation is undone).  `copy`
+// makes it the identity.
 template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_gate2(V (&v)[P], V (&l)[P], const TGate<R>& g,
-                                            double* __restrict__ part_out, uint32_t tid) {
-    if (g.kind == DK_ROT) {
+__device__ __forceinline__ void apply_gate2(const V (&sv)[P], V (&dv)[P], const V (&sl)[P], V (&dl)[P],
+                                            const TGate<R>& g, bool copy, double* __restrict__ part_out,
+                                            uint32_t tid) {
+    if (!copy && g.kind == DK_ROT) {
         double part = 0.0;
         on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) {
             constexpr int b = decltype(B)::value;
-            if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(v, l);
-            else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(v, l);
-            else part = rot_part<b, QSV_AXIS_Z>(v, l);
-            rg_1q<b>(v, g.m);
-            rg_1q<b>(l, g.m);
+            if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(sv, sl);
+            else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(sv, sl);
+            else part = rot_part<b, QSV_AXIS_Z>(sv, sl);
+            rg_1q<b>(sv, dv, g.m);
+            rg_1q<b>(sl, dl, g.m);
         });
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if ((tid & 63) == 0) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
     } else {
-        apply_gate<RB>(v, g);
-        apply_gate<RB>(l, g);
+        const int op = copy ? kOpCopy : g.kind * 64 + g.r0 * 8 + g.r1;
+        apply_op<RB>(sv, dv, op, g.m);
+        apply_op<RB>(sl, dl, op, g.m);
     }
 }
 
@@ -188,14 +193,22 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
                 l[u] = *reinterpret_cast<const V*>(ll + (sb ^ S.su[u]));
             }
         }
-        for (int g = S.gbeg; g < S.gend; ++g) apply_gate2<RB>(v, l, gates[g], part_out, tid);
+        {
+            // two gates per iteration, alternating register sets (no copies)
+            V vw[P], lw[P];
+            for (int g = S.gbeg; g < S.gend; g += 2) {
+                apply_gate2<RB>(v, vw, l, lw, gates[g], false, part_out, tid);
+                const bool two = g + 1 < S.gend;
+                apply_gate2<RB>(vw, v, lw, l, gates[two ? g + 1 : g], !two, part_out, tid);
+            }
+        }
         if (st < nst - 1) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
-                *reinterpret_cast<V*>(lp + (sb ^ S.su[u])) = v[u];
-                *reinterpret_cast<V*>(ll + (sb ^ S.su[u])) = l[u];
+                *reinterpret_cast<V*>(lp + (sb ^ S.su_wr[u])) = v[u];
+                *reinterpret_cast<V*>(ll + (sb ^ S.su_wr[u])) = l[u];
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
     const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);

@@ -155,6 +155,7 @@ hipError_t plan_staging(qsv_ctx ctx, size_t bytes, void** host) {
 
 hipError_t plan_upload(qsv_ctx ctx, size_t bytes, void** dev) {
     hipError_t e;
+    ctx->plan_resident = false;   // d_plan is about to hold something else
     if (bytes > ctx->d_plan_bytes) {
         e = hipStreamSynchronize(ctx->stream);   // older passes may still read d_plan
         if (e != hipSuccess) return e;
@@ -427,6 +428,55 @@ qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u) {
     return QSV_OK;
 }
 
+static bool same_gates(const std::vector<PGate>& a, const std::vector<PGate>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const PGate& x = a[i];
+        const PGate& y = b[i];
+        if (x.kind != y.kind || x.p0 != y.p0 || x.p1 != y.p1 || x.cs != y.cs || x.tag != y.tag ||
+            std::memcmp(x.m, y.m, sizeof(x.m)) != 0)
+            return false;
+    }
+    return true;
+}
+
+static bool same_cfg(const TileConfig& a, const TileConfig& b) {
+    return a.tile_bits == b.tile_bits && a.low_bits == b.low_bits && a.reg_bits == b.reg_bits &&
+           a.coal_bits == b.coal_bits;
+}
+
+// Fused application of lowered gates on one state.  Fusion, planning and
+// the device records are reused while the circuit and the tile shape stay
+// the same (the common case of repeated evaluation), so a repeated call
+// costs one comparison on the host and no upload.
+static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<PGate>&& pg) {
+    const TileConfig& cfg = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    const bool hit = ctx->cache_n == n && ctx->cache_dtype == dtype && same_cfg(ctx->cache_cfg, cfg) &&
+                     same_gates(ctx->cache_in, pg);
+    if (!hit) {
+        ctx->cache_n = -1;
+        ctx->plan_resident = false;
+        ctx->cache_pg = prefuse(pg);
+        ctx->cache_passes = plan_passes(n, ctx->cache_pg, cfg);
+        ctx->cache_in = std::move(pg);
+        ctx->cache_n = n;
+        ctx->cache_dtype = dtype;
+        ctx->cache_cfg = cfg;
+    }
+    if (log_enabled()) {
+        size_t stages = 0, singles = 0;
+        for (const Pass& p : ctx->cache_passes) {
+            stages += p.stages.size();
+            singles += p.single ? 1 : 0;
+        }
+        logf("apply_circuit: n=%d %zu gates -> %zu after fusion, %zu passes (%zu single-gate), "
+             "%zu register stages, tile 2^%d low %d, plan %s",
+             n, ctx->cache_in.size(), ctx->cache_pg.size(), ctx->cache_passes.size(), singles, stages,
+             cfg.tile_bits, cfg.low_bits, hit ? (ctx->plan_resident ? "reused" : "re-uploaded") : "new");
+    }
+    return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->cache_passes, true);
+}
+
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags) {
     if (qsv_status s = check_state(st)) return s;
@@ -442,21 +492,7 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
             HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
         return QSV_OK;
     }
-    const TileConfig& cfg = st->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
-    const size_t ng_in = pg.size();
-    pg = prefuse(pg);
-    std::vector<Pass> passes = plan_passes(st->n, pg, cfg);
-    if (log_enabled()) {
-        size_t stages = 0, singles = 0;
-        for (const Pass& p : passes) {
-            stages += p.stages.size();
-            singles += p.single ? 1 : 0;
-        }
-        logf("apply_circuit: n=%d %zu gates -> %zu after fusion, %zu passes (%zu single-gate), "
-             "%zu register stages, tile 2^%d low %d",
-             st->n, ng_in, pg.size(), passes.size(), singles, stages, cfg.tile_bits, cfg.low_bits);
-    }
-    HIP_OR_FAIL(ctx, run_passes(ctx, st->ptr, st->n, st->dtype, pg, passes), "tile passes");
+    HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg)), "tile passes");
     return QSV_OK;
 }
 
@@ -598,10 +634,7 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
                 for (const PGate& x : fwd)
                     HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
             } else {
-                const TileConfig& cfg = psi->dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
-                const std::vector<PGate> fused = prefuse(fwd);
-                HIP_OR_FAIL(ctx, run_passes(ctx, psi->ptr, n, psi->dtype, fused,
-                                            plan_passes(n, fused, cfg)),
+                HIP_OR_FAIL(ctx, run_fused(ctx, psi->ptr, n, psi->dtype, std::vector<PGate>(fwd)),
                             "forward passes");
             }
         }

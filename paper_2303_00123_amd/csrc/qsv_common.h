@@ -31,29 +31,47 @@ __device__ __forceinline__ uint32_t insert0_32(uint32_t j, int p) {
     return ((j ^ lo) << 1) | lo;
 }
 
+// Fused multiply-add in the state's real type.
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Complex multiply-accumulate chains: each term is two fused multiply-adds
+// on the real part and two on the imaginary part; the first term starts
+// from a product.
+template <typename R, typename V>
+__device__ __forceinline__ void cmac_first(R ur, R ui, const V& x, R& re, R& im) {
+    re = fmaR(-ui, x.y, ur * x.x);
+    im = fmaR(ui, x.x, ur * x.y);
+}
+template <typename R, typename V>
+__device__ __forceinline__ void cmac(R ur, R ui, const V& x, R& re, R& im) {
+    re = fmaR(ur, x.x, re);
+    re = fmaR(-ui, x.y, re);
+    im = fmaR(ur, x.y, im);
+    im = fmaR(ui, x.x, im);
+}
+
 // (oa, ob) = U (a, b) for a 2x2 complex U.
 template <typename R, typename V>
 __device__ __forceinline__ void mv2(const R* u, const V& a, const V& b, V& oa, V& ob) {
-    oa.x = u[0] * a.x - u[1] * a.y + u[2] * b.x - u[3] * b.y;
-    oa.y = u[0] * a.y + u[1] * a.x + u[2] * b.y + u[3] * b.x;
-    ob.x = u[4] * a.x - u[5] * a.y + u[6] * b.x - u[7] * b.y;
-    ob.y = u[4] * a.y + u[5] * a.x + u[6] * b.y + u[7] * b.x;
+    R r0, i0, r1, i1;
+    cmac_first(u[0], u[1], a, r0, i0);
+    cmac(u[2], u[3], b, r0, i0);
+    cmac_first(u[4], u[5], a, r1, i1);
+    cmac(u[6], u[7], b, r1, i1);
+    oa.x = r0; oa.y = i0;
+    ob.x = r1; ob.y = i1;
 }
 
-// o[r] = sum_c U[r][c] v[c] for a 4x4 complex U (accumulation starts from
-// the first product, so every term is one multiply-add).
+// o[r] = sum_c U[r][c] v[c] for a 4x4 complex U.
 template <typename R, typename V>
 __device__ __forceinline__ void mv4(const R* u, const V* v, V* o) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        R re = u[8 * r] * v[0].x - u[8 * r + 1] * v[0].y;
-        R im = u[8 * r] * v[0].y + u[8 * r + 1] * v[0].x;
+        R re, im;
+        cmac_first(u[8 * r], u[8 * r + 1], v[0], re, im);
 #pragma unroll
-        for (int c = 1; c < 4; ++c) {
-            const R ur = u[2 * (4 * r + c)], ui = u[2 * (4 * r + c) + 1];
-            re += ur * v[c].x - ui * v[c].y;
-            im += ur * v[c].y + ui * v[c].x;
-        }
+        for (int c = 1; c < 4; ++c) cmac(u[2 * (4 * r + c)], u[2 * (4 * r + c) + 1], v[c], re, im);
         o[r].x = re;
         o[r].y = im;
     }

@@ -109,7 +109,9 @@ struct TGate {
 struct TStage {
     int32_t gbeg, gend;     // gate range [gbeg, gend) of the pass's gate array
     int32_t tbits[10];      // thread-id bit j <-> local bit
-    uint32_t su[32];        // byte offset (after the LDS swizzle) of register slot u
+    uint32_t su[32];        // byte offset (after the LDS swizzle) of register slot u (reads)
+    uint32_t su_wr[32];     // the same for the write at the stage's end: su of the slot the
+                            // amplitude belongs to after the stage's trailing permutation gates
 };
 
 // Pass header in device memory; followed by nstages TStage records and then
@@ -188,6 +190,16 @@ struct qsv_ctx_s {
     // autotuner choices: batch shape key -> (tile_bits, low_bits)
     std::map<uint64_t, std::pair<int, int>> tuned;
     bool tune_loaded = false;
+
+    // plan of the last fused circuit: reused while the lowered gates, the
+    // qubit count, the precision and the tile shape are unchanged
+    std::vector<qsv::PGate> cache_in;   // lowered gates the plan was made from
+    int cache_n = -1;
+    int cache_dtype = 0;
+    qsv::TileConfig cache_cfg{0, 0, 0, 0};
+    std::vector<qsv::PGate> cache_pg;   // fused gates
+    std::vector<qsv::Pass> cache_passes;
+    bool plan_resident = false;         // d_plan holds cache_passes' records
 };
 
 struct qsv_state_s {
@@ -248,8 +260,10 @@ size_t pass_record_bytes(int dtype, const Pass& ps);
 bool write_pass_record(int dtype, char* dst, const std::vector<PGate>& gates, const Pass& ps);
 
 // Tile passes: uploads the plan for all passes, then launches them in order.
+// cached: the passes are ctx->cache_passes; their records are uploaded only
+// if d_plan no longer holds them.
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
-                      const std::vector<Pass>& passes);
+                      const std::vector<Pass>& passes, bool cached = false);
 
 // Reductions.  Stage-1 partials go to ctx scratch; results land in host memory.
 // Z-string sums: out[t] = sum_x |s_x|^2 (-1)^{popcount(x & pmask[t])}, t < nt.

@@ -16,6 +16,10 @@
 //
 // LDS holds the tile with an XOR swizzle on the 16-byte (c128) or 8-byte
 // (c64) slot index, so strided stage mappings spread over the banks.
+#include <array>
+#include <cstdlib>
+#include <vector>
+
 #include "qsv_tile_core.h"
 
 namespace qsv {
@@ -62,6 +66,7 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
 
 // ------------------------------------------------------------ host side
 bool is_zero(double x) { return x == 0.0; }
+
 
 // Lower a host gate to the device record of its stage.  Returns false if a
 // gate bit is not a register bit of the stage (a planner bug).
@@ -173,6 +178,51 @@ size_t record_bytes_t(const Pass& ps) {
     return (b + 255) & ~size_t(255);
 }
 
+// If the gate's matrix is a permutation matrix with unit entries (X, CX on
+// either control state, SWAP), fill pi (if given) with the local-index map
+// x -> row of the 1 in column x, and return true.  Local index: 1q -> the
+// target bit; two positions -> 2*x_p0 + x_p1 (control = p0 for controlled).
+bool permutation_of(const PGate& g, int* pi) {
+    if (g.kind == KROT) return false;
+    double m4[32];
+    int d;
+    if (g.kind == QSV_G1Q) {
+        d = 2;
+        for (int i = 0; i < 8; ++i) m4[i] = g.m[i];
+    } else if (g.kind == QSV_GC1Q) {
+        d = 4;
+        for (int i = 0; i < 32; ++i) m4[i] = 0.0;
+        const int c1 = g.cs & 1, c0 = 1 - c1;
+        m4[2 * (4 * (2 * c0) + 2 * c0)] = 1.0;
+        m4[2 * (4 * (2 * c0 + 1) + 2 * c0 + 1)] = 1.0;
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                m4[2 * (4 * (2 * c1 + r) + 2 * c1 + c)] = g.m[2 * (2 * r + c)];
+                m4[2 * (4 * (2 * c1 + r) + 2 * c1 + c) + 1] = g.m[2 * (2 * r + c) + 1];
+            }
+    } else {
+        d = 4;
+        for (int i = 0; i < 32; ++i) m4[i] = g.m[i];
+    }
+    int p[4] = {-1, -1, -1, -1};
+    for (int c = 0; c < d; ++c)
+        for (int r = 0; r < d; ++r) {
+            const double re = m4[2 * (d * r + c)], im = m4[2 * (d * r + c) + 1];
+            if (im != 0.0) return false;
+            if (re == 1.0) {
+                if (p[c] >= 0) return false;
+                p[c] = r;
+            } else if (re != 0.0) {
+                return false;
+            }
+        }
+    for (int c = 0; c < d; ++c)
+        if (p[c] < 0) return false;
+    if (pi)
+        for (int c = 0; c < d; ++c) pi[c] = p[c];
+    return true;
+}
+
 // Fill the device record of a tile pass at h.  False on a planner bug.
 template <typename R>
 bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
@@ -189,9 +239,60 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
     hd->rb = rb;
     hd->pad2 = 0;
     if (ps.stages.empty()) return false;
+    const int ns = int(ps.stages.size());
+    // Each stage's gates; trailing permutation gates (X, CX, SWAP: 0/1
+    // matrices) whose bits no later gate of the stage touches are not run:
+    // they only decide where each register slot is written at the stage's
+    // end.  dest[si][u] = slot whose position slot u's amplitude takes.
+    std::vector<std::vector<PGate>> run(static_cast<size_t>(ns));
+    std::vector<std::array<int, 32>> dest(static_cast<size_t>(ns));
+    for (int si = 0; si < ns; ++si) {
+        const Stage& st = ps.stages[size_t(si)];
+        int reg[32];
+        for (int x = 0; x < 32; ++x) reg[x] = -1;
+        for (int j = 0; j < st.nr; ++j) reg[st.rbits[j]] = j;
+        std::vector<PGate> fused = fuse_stage(gates, st.gates);
+        std::vector<char> virt(fused.size(), 0);
+        uint32_t touched = 0;   // register bits used by later gates that run
+        for (size_t i = fused.size(); i-- > 0;) {
+            const PGate& fg = fused[i];
+            const int b0 = loc[fg.p0] >= 0 ? reg[loc[fg.p0]] : -1;
+            const int b1 = is_1q(fg.kind) ? b0 : (loc[fg.p1] >= 0 ? reg[loc[fg.p1]] : -1);
+            if (b0 < 0 || b1 < 0) return false;
+            const uint32_t bits = (1u << b0) | (1u << b1);
+            if (!(bits & touched) && permutation_of(fg, nullptr)) virt[i] = 1;
+            else touched |= bits;
+        }
+        std::array<int, 32>& D = dest[size_t(si)];
+        for (int u = 0; u < 32; ++u) D[u] = u;
+        for (size_t i = 0; i < fused.size(); ++i) {
+            if (!virt[i]) {
+                run[size_t(si)].push_back(fused[i]);
+                continue;
+            }
+            // local index of the gate: 1q -> bit of p0; 2-position -> 2*x_p0 + x_p1
+            const PGate& fg = fused[i];
+            int pi[4];
+            permutation_of(fg, pi);
+            const int b0 = reg[loc[fg.p0]];
+            const int b1 = is_1q(fg.kind) ? -1 : reg[loc[fg.p1]];
+            for (int u = 0; u < (1 << rb); ++u) {
+                const int x = D[u];
+                const int li = b1 < 0 ? ((x >> b0) & 1) : (((x >> b0) & 1) << 1) | ((x >> b1) & 1);
+                const int lo = pi[li];
+                int y = x;
+                if (b1 < 0) {
+                    y = (y & ~(1 << b0)) | ((lo & 1) << b0);
+                } else {
+                    y = (y & ~((1 << b0) | (1 << b1))) | (((lo >> 1) & 1) << b0) | ((lo & 1) << b1);
+                }
+                D[u] = y;
+            }
+        }
+    }
     // load mapping = first stage's, store mapping = last stage's: thread bits
     // are the complement of the register bits, ascending
-    auto mapping = [&](const Stage& st, int32_t* tpos, uint64_t* du) {
+    auto mapping = [&](const Stage& st, const int* perm, int32_t* tpos, uint64_t* du) {
         uint32_t used = 0;
         for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
         int tj = 0;
@@ -200,19 +301,23 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
         for (; tj < 10; ++tj) tpos[tj] = 0;
         for (int u = 0; u < 32; ++u) {
             uint64_t off = 0;
-            if (u < (1 << rb))
+            if (u < (1 << rb)) {
+                const int x = perm[u];
                 for (int j = 0; j < rb; ++j)
-                    if ((u >> j) & 1) off |= uint64_t(1) << ps.pos[st.rbits[j]];
+                    if ((x >> j) & 1) off |= uint64_t(1) << ps.pos[st.rbits[j]];
+            }
             du[u] = off;
         }
     };
-    mapping(ps.stages.front(), hd->tpos_ld, hd->du);
-    mapping(ps.stages.back(), hd->tpos_st, hd->du_st);
+    static const int ident[32] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15,
+                                  16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
+    mapping(ps.stages.front(), ident, hd->tpos_ld, hd->du);
+    mapping(ps.stages.back(), dest[size_t(ns - 1)].data(), hd->tpos_st, hd->du_st);
     TStage* ts = reinterpret_cast<TStage*>(h + sizeof(TPassHdr));
     TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + sizeof(TPassHdr) + ps.stages.size() * sizeof(TStage));
     int gi = 0;
-    for (size_t si = 0; si < ps.stages.size(); ++si) {
-        const Stage& st = ps.stages[si];
+    for (int si = 0; si < ns; ++si) {
+        const Stage& st = ps.stages[size_t(si)];
         ts[si].gbeg = gi;
         uint32_t used = 0;
         for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
@@ -220,14 +325,18 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
         for (int b = 0; b < ps.k && tj < 10; ++b)
             if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
         for (; tj < 10; ++tj) ts[si].tbits[tj] = 0;
-        for (int u = 0; u < 32; ++u) {
+        auto slot_off = [&](int u) {
             uint32_t e = 0;
-            if (u < (1 << st.nr))
-                for (int j = 0; j < st.nr; ++j)
-                    if ((u >> j) & 1) e |= 1u << st.rbits[j];
-            ts[si].su[u] = tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
+            for (int j = 0; j < st.nr; ++j)
+                if ((u >> j) & 1) e |= 1u << st.rbits[j];
+            return tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
+        };
+        for (int u = 0; u < 32; ++u) {
+            const bool in = u < (1 << st.nr);
+            ts[si].su[u] = in ? slot_off(u) : 0;
+            ts[si].su_wr[u] = in ? slot_off(dest[size_t(si)][u]) : 0;
         }
-        for (const PGate& fg : fuse_stage(gates, st.gates))
+        for (const PGate& fg : run[size_t(si)])
             if (!to_device_gate<R>(fg, loc, st, tg[gi++])) return false;
         ts[si].gend = gi;
     }
@@ -237,7 +346,7 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
 
 template <typename R>
 hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& gates,
-                        const std::vector<Pass>& passes) {
+                        const std::vector<Pass>& passes, bool cached) {
     using V = typename V2T<R>::type;
     // upload layout: one record per tile pass
     size_t bytes = 0;
@@ -250,7 +359,9 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         bytes += record_bytes_t<R>(passes[i]);
     }
     char* dev = nullptr;
-    if (bytes) {
+    if (bytes && cached && ctx->plan_resident) {
+        dev = static_cast<char*>(ctx->d_plan);
+    } else if (bytes) {
         void* host = nullptr;
         hipError_t e = plan_staging(ctx, bytes, &host);
         if (e != hipSuccess) return e;
@@ -262,6 +373,7 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         e = plan_upload(ctx, bytes, &d);
         if (e != hipSuccess) return e;
         dev = static_cast<char*>(d);
+        ctx->plan_resident = cached;
     }
     const char* pname = sizeof(R) == 8 ? "tile_pass_c128" : "tile_pass_c64";
     const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
@@ -303,9 +415,9 @@ bool tile_shape_supported(int dtype, int tile_bits, int reg_bits) {
 int tile_bits_max(int dtype) { return dtype == QSV_C128 ? TileK<double>::value : TileK<float>::value; }
 
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
-                      const std::vector<Pass>& passes) {
-    return dtype == QSV_C128 ? run_passes_t<double>(ctx, s, n, gates, passes)
-                             : run_passes_t<float>(ctx, s, n, gates, passes);
+                      const std::vector<Pass>& passes, bool cached) {
+    return dtype == QSV_C128 ? run_passes_t<double>(ctx, s, n, gates, passes, cached)
+                             : run_passes_t<float>(ctx, s, n, gates, passes, cached);
 }
 
 }  // namespace qsv

@@ -43,80 +43,79 @@ __device__ __forceinline__ uint32_t deposit32(uint32_t e, const int32_t* pos, in
 template <int B>
 using IC = std::integral_constant<int, B>;
 
+// Workgroup barrier that orders LDS accesses only: it waits for this
+// thread's outstanding LDS operations but not for global loads, so loads
+// issued ahead (the next tile's amplitudes) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------- register gate bodies
+// Each body reads the amplitudes from s and writes every slot of d (slots
+// the gate leaves alone are copied), so results never overwrite inputs that
+// are still live and need no register copies afterwards.
 template <int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_1q(V (&v)[P], const R* m) {
+__device__ __forceinline__ void rg_1q(const V (&s)[P], V (&d)[P], const R* m) {
 #pragma unroll
     for (int i = 0; i < P; ++i)
-        if (!(i & (1 << B))) {
-            const V a = v[i], b = v[i | (1 << B)];
-            mv2(m, a, b, v[i], v[i | (1 << B)]);
-        }
+        if (!(i & (1 << B))) mv2(m, s[i], s[i | (1 << B)], d[i], d[i | (1 << B)]);
 }
 
 template <typename R, typename V>
 __device__ __forceinline__ V cmul(const V& a, R dr, R di) {
     V o;
-    o.x = a.x * dr - a.y * di;
-    o.y = a.x * di + a.y * dr;
+    o.x = fmaR(-a.y, di, a.x * dr);
+    o.y = fmaR(a.y, dr, a.x * di);
     return o;
 }
 
 template <int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_1d(V (&v)[P], const R* m) {
+__device__ __forceinline__ void rg_1d(const V (&s)[P], V (&d)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) d[i] = (i & (1 << B)) ? cmul(s[i], m[2], m[3]) : cmul(s[i], m[0], m[1]);
+}
+
+template <int C, int T, typename R, typename V, int P>
+__device__ __forceinline__ void rg_c1q(const V (&s)[P], V (&d)[P], const R* m) {
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-        if (i & (1 << B)) v[i] = cmul(v[i], m[2], m[3]);
-        else v[i] = cmul(v[i], m[0], m[1]);
+        if (!((i >> C) & 1)) d[i] = s[i];
+        else if (!(i & (1 << T))) mv2(m, s[i], s[i | (1 << T)], d[i], d[i | (1 << T)]);
     }
 }
 
-template <int C, int T, int CS, typename R, typename V, int P>
-__device__ __forceinline__ void rg_c1q(V (&v)[P], const R* m) {
+template <int C, int T, typename V, int P>
+__device__ __forceinline__ void rg_cx(const V (&s)[P], V (&d)[P]) {
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
-            const V a = v[i], b = v[i | (1 << T)];
-            mv2(m, a, b, v[i], v[i | (1 << T)]);
-        }
+    for (int i = 0; i < P; ++i) d[i] = ((i >> C) & 1) ? s[i ^ (1 << T)] : s[i];
 }
 
-template <int C, int T, int CS, typename V, int P>
-__device__ __forceinline__ void rg_cx(V (&v)[P]) {
+template <int C, int T, typename R, typename V, int P>
+__device__ __forceinline__ void rg_cd(const V (&s)[P], V (&d)[P], const R* m) {
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS && !(i & (1 << T))) {
-            const V a = v[i];
-            v[i] = v[i | (1 << T)];
-            v[i | (1 << T)] = a;
-        }
-}
-
-template <int C, int T, int CS, typename R, typename V, int P>
-__device__ __forceinline__ void rg_cd(V (&v)[P], const R* m) {
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (((i >> C) & 1) == CS) {
-            if (i & (1 << T)) v[i] = cmul(v[i], m[2], m[3]);
-            else v[i] = cmul(v[i], m[0], m[1]);
-        }
+    for (int i = 0; i < P; ++i) {
+        if (!((i >> C) & 1)) d[i] = s[i];
+        else d[i] = (i & (1 << T)) ? cmul(s[i], m[2], m[3]) : cmul(s[i], m[0], m[1]);
+    }
 }
 
 template <int A, int B, typename R, typename V, int P>
-__device__ __forceinline__ void rg_2q(V (&v)[P], const R* m) {
+__device__ __forceinline__ void rg_2q(const V (&s)[P], V (&d)[P], const R* m) {
 #pragma unroll
     for (int i = 0; i < P; ++i)
         if (!(i & (1 << A)) && !(i & (1 << B))) {
             V in[4], out[4];
-            in[0] = v[i];
-            in[1] = v[i | (1 << B)];
-            in[2] = v[i | (1 << A)];
-            in[3] = v[i | (1 << A) | (1 << B)];
+            in[0] = s[i];
+            in[1] = s[i | (1 << B)];
+            in[2] = s[i | (1 << A)];
+            in[3] = s[i | (1 << A) | (1 << B)];
             mv4(m, in, out);
-            v[i] = out[0];
-            v[i | (1 << B)] = out[1];
-            v[i | (1 << A)] = out[2];
-            v[i | (1 << A) | (1 << B)] = out[3];
+            d[i] = out[0];
+            d[i | (1 << B)] = out[1];
+            d[i | (1 << A)] = out[2];
+            d[i | (1 << A) | (1 << B)] = out[3];
         }
 }
 
@@ -134,42 +133,82 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
     }
 }
 
-// Controlled kinds are emitted for control state 1 only (the host lowers a
-// control-state-0 gate to a 2-qubit gate), and 2-qubit gates with r0 < r1
-// (the host permutes the matrix), which keeps the number of compiled
-// specialisations -- and the kernel's instruction footprint -- small.
+// d = gate(s).  One flat switch over (kind, r0, r1): every reachable case
+// applies a gate, so each case can produce its results directly in the
+// registers the join expects.  Controlled kinds are emitted for control
+// state 1 only (the host lowers a control-state-0 gate to a 2-qubit gate),
+// and 2-qubit gates with r0 < r1 (the host permutes the matrix), which keeps
+// the number of compiled cases -- and the instruction footprint -- small.
+#define QSV_C1(KD, B)                                                          \
+    case (KD) * 64 + (B) * 8:                                                  \
+        if constexpr ((B) < RB) {                                              \
+            if constexpr ((KD) == DK_1Q) rg_1q<(B)>(s, d, g.m);                \
+            else rg_1d<(B)>(s, d, g.m);                                        \
+        } else {                                                               \
+            __builtin_unreachable();                                           \
+        }                                                                      \
+        break;
+#define QSV_C2(KD, A, B)                                                       \
+    case (KD) * 64 + (A) * 8 + (B):                                            \
+        if constexpr ((A) < RB && (B) < RB && (A) != (B) && ((KD) != DK_2Q || (A) < (B))) { \
+            if constexpr ((KD) == DK_2Q) rg_2q<(A), (B)>(s, d, g.m);           \
+            else if constexpr ((KD) == DK_CX) rg_cx<(A), (B)>(s, d);           \
+            else if constexpr ((KD) == DK_CD) rg_cd<(A), (B)>(s, d, g.m);      \
+            else rg_c1q<(A), (B)>(s, d, g.m);                                  \
+        } else {                                                               \
+            __builtin_unreachable();                                           \
+        }                                                                      \
+        break;
+#define QSV_C2ROW(KD, A) \
+    QSV_C2(KD, A, 0) QSV_C2(KD, A, 1) QSV_C2(KD, A, 2) QSV_C2(KD, A, 3) QSV_C2(KD, A, 4) QSV_C2(KD, A, 5)
+#define QSV_C2ALL(KD) \
+    QSV_C2ROW(KD, 0) QSV_C2ROW(KD, 1) QSV_C2ROW(KD, 2) QSV_C2ROW(KD, 3) QSV_C2ROW(KD, 4) QSV_C2ROW(KD, 5)
+#define QSV_C1ALL(KD) QSV_C1(KD, 0) QSV_C1(KD, 1) QSV_C1(KD, 2) QSV_C1(KD, 3) QSV_C1(KD, 4) QSV_C1(KD, 5)
+
+// Opcode of a gate: kind * 64 + r0 * 8 + r1; kOpCopy is d = s.
+constexpr int kOpCopy = 7 * 64;
+
 template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_gate(V (&v)[P], const TGate<R>& g) {
-    const int kind = g.kind;
-    if (kind == DK_1Q) {
-        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1q<decltype(B)::value>(v, g.m); });
-    } else if (kind == DK_1D) {
-        on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) { rg_1d<decltype(B)::value>(v, g.m); });
-    } else if (kind == DK_2Q) {
-        on_bit<RB>(g.r0, [&](auto A) __attribute__((always_inline)) {
-            on_bit<RB>(g.r1, [&](auto B) __attribute__((always_inline)) {
-                if constexpr (decltype(A)::value < decltype(B)::value)
-                    rg_2q<decltype(A)::value, decltype(B)::value>(v, g.m);
-            });
-        });
-    } else {
-        on_bit<RB>(g.r0, [&](auto C) __attribute__((always_inline)) {
-            on_bit<RB>(g.r1, [&](auto T) __attribute__((always_inline)) {
-                constexpr int c = decltype(C)::value, t = decltype(T)::value;
-                if constexpr (c != t) {
-                    if (kind == DK_CX) rg_cx<c, t, 1>(v);
-                    else if (kind == DK_CD) rg_cd<c, t, 1>(v, g.m);
-                    else rg_c1q<c, t, 1>(v, g.m);
-                }
-            });
-        });
+__device__ __forceinline__ void apply_op(const V (&s)[P], V (&d)[P], int op, const R* m) {
+    struct { const R* m; } g{m};
+    switch (op) {
+    case kOpCopy:
+#pragma unroll
+        for (int u = 0; u < P; ++u) d[u] = s[u];
+        break;
+        QSV_C1ALL(DK_1Q)
+        QSV_C1ALL(DK_1D)
+        QSV_C2ALL(DK_C1Q)
+        QSV_C2ALL(DK_CX)
+        QSV_C2ALL(DK_CD)
+        QSV_C2ALL(DK_2Q)
+    default: __builtin_unreachable();
     }
 }
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_gate(const V (&s)[P], V (&d)[P], const TGate<R>& g) {
+    apply_op<RB>(s, d, g.kind * 64 + g.r0 * 8 + g.r1, g.m);
+}
+#undef QSV_C1ALL
+#undef QSV_C2ALL
+#undef QSV_C2ROW
+#undef QSV_C2
+#undef QSV_C1
 
+// Gates [gb, ge) on v, two per iteration: the first writes w, the second
+// writes v back, so every result lands in the registers its reader expects
+// without copies; an odd count ends with a copy in place of the second.
 template <int RB, typename R, typename V, int P>
 __device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restrict__ gates, int gb,
                                             int ge) {
-    for (int g = gb; g < ge; ++g) apply_gate<RB>(v, gates[g]);
+    V w[P];
+    for (int g = gb; g < ge; g += 2) {
+        const TGate<R>& a = gates[g];
+        apply_op<RB>(v, w, a.kind * 64 + a.r0 * 8 + a.r1, a.m);
+        const bool two = g + 1 < ge;
+        const TGate<R>& b = gates[two ? g + 1 : g];
+        apply_op<RB>(w, v, two ? b.kind * 64 + b.r0 * 8 + b.r1 : kOpCopy, b.m);
+    }
 }
 
 // Run stages of a pass on the register-resident amplitudes v: stage 0 and
@@ -193,8 +232,8 @@ __device__ __forceinline__ void run_stages(V (&v)[1 << RB], char* lds, const TSt
         apply_range<RB>(v, gates, S.gbeg, S.gend);
         if (st < nst - 1) {
 #pragma unroll
-            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su[u])) = v[u];
-            __syncthreads();
+            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su_wr[u])) = v[u];
+            lds_barrier();
         }
     }
 }

@@ -7,8 +7,11 @@ synthetic.  One step = init |0...0> + the whole circuit (fused tile passes)
 + norm + <Z_0 Z_29>.  value = gates / second over the timed steps.
 
 Also reported (same JSON line):
-  roofline      achieved HBM GB/s of the dominant kernel (fused tile pass),
-                from HIP events on the library's stream over the timed steps
+  roofline      the dominant kernel (fused tile pass) from HIP events on the
+                library's stream over the timed steps: algorithmic flops
+                (FP64 for complex128) and bytes per launch over the average
+                launch time, against MI355X peaks; `bound` is the resource
+                whose time at peak is longer
   cpu_baseline  the FP64 CPU oracle on the same 30-qubit circuit, first gates
                 only (time-bounded sample), on this host's cores
   extras        complex64 throughput of the same circuit; unfused per-gate
@@ -29,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector FP64 / FP32
 METRIC = "gates/s + HBM GB/s (% peak) at 30 qubits; adjoint-grad time / forward time"
 
 
@@ -65,21 +69,61 @@ def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20,
     del st
     ctx.close()
     torch.cuda.empty_cache()
+    flops = sum(gate_flops_per_amp(x) for x in c.gates) * float(2 ** n)
     return {"gates": len(c.gates), "seconds": t1 - t0, "prof": prof, "norm": norm,
-            "zz": float(terms[0])}
+            "zz": float(terms[0]), "flops_per_step": flops}
 
 
-def kernel_roofline(prof: dict, name: str):
+def gate_flops_per_amp(gate) -> float:
+    """Algorithmic real flops per amplitude of one gate, as Algs. 1-3 apply
+    it: a dense 2x2 costs 2 complex multiplies + 1 complex add per output
+    (14 per amplitude), a controlled 2x2 touches half the amplitudes (7), a
+    dense 4x4 costs 4 multiplies + 3 adds per output (30); a diagonal 2x2
+    is one complex multiply per amplitude (6, half that when controlled);
+    permutation matrices (X, CNOT, SWAP) move data and do no arithmetic."""
+    import numpy as np
+    if gate.kind == "rot":
+        return 6.0 if str(gate.axis).lower() == "z" else 14.0
+    m = np.asarray(gate.matrix)
+    if np.all((m == 0) | (m == 1)) and np.all(m.sum(axis=0) == 1):
+        return 0.0
+    diag = np.count_nonzero(m - np.diag(np.diag(m))) == 0
+    if gate.kind == "1q":
+        return 6.0 if diag else 14.0
+    if gate.kind == "c1q":
+        return 3.0 if diag else 7.0
+    return 6.0 if diag else 30.0
+
+
+def kernel_roofline(prof: dict, name: str, steps: int, flops_per_step: float, dtype: str):
+    """Roofline of the dominant kernel from its average launch duration:
+    algorithmic bytes (one read + one write of the state) and algorithmic
+    flops (the circuit's gates, spread over the step's launches) per launch.
+    `bound` is whichever takes longer at its peak; the other is reported
+    alongside."""
     k = prof.get(name)
     if not k or k["launches"] == 0 or k["ms"] <= 0:
         return None
     per_launch_bytes = k["bytes"] / k["launches"]
+    per_launch_flops = flops_per_step / (k["launches"] / steps)
     avg_s = k["ms"] / k["launches"] / 1e3
-    achieved = per_launch_bytes / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": name, "launches": k["launches"], "avg_ms": round(k["ms"] / k["launches"], 4),
-            "bytes_per_launch": per_launch_bytes}
+    gbs = per_launch_bytes / avg_s / 1e9
+    tfl = per_launch_flops / avg_s / 1e12
+    peak_tf = PEAK_TFLOPS[dtype]
+    hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    alu = {"bound": "alu", "achieved": round(tfl, 2), "peak": peak_tf, "unit": "TFLOP/s",
+           "frac": round(tfl / peak_tf, 4)}
+    alu_time = per_launch_flops / (peak_tf * 1e12)
+    hbm_time = per_launch_bytes / (PEAK_HBM_GBS * 1e9)
+    main, other = (alu, hbm) if alu_time >= hbm_time else (hbm, alu)
+    out = dict(main)
+    out.update({"traffic": None, "kernel": name, "launches": k["launches"],
+                "avg_ms": round(k["ms"] / k["launches"], 4), "bytes_per_launch": per_launch_bytes,
+                "flops_per_launch": per_launch_flops,
+                "time_at_peak_ms": {"alu": round(alu_time * 1e3, 3), "hbm": round(hbm_time * 1e3, 3)},
+                "other": other})
+    return out
 
 
 def measured_traffic(n: int):
@@ -239,7 +283,8 @@ def main():
                     help="only run a device copy of 2^k complex128 amplitudes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the path runs on one MI355X per process; --gpus must be 1 "
+                                   "(the multi-GPU layout is a design, not a measured path)"}))
         sys.exit(2)
 
     import torch
@@ -262,7 +307,7 @@ def main():
     log(f"primary: n={args.n} c128 steps={args.steps} warmup={args.warmup}")
     r = primary(q, W, args.n, q.QSV_C128, args.steps, args.warmup)
     value = r["gates"] * args.steps / r["seconds"]
-    roof = kernel_roofline(r["prof"], "tile_pass_c128")
+    roof = kernel_roofline(r["prof"], "tile_pass_c128", args.steps, r["flops_per_step"], "f64")
     if roof is not None:
         roof["traffic"] = measured_traffic(args.n)
     log(f"primary: {value:.1f} gates/s, roofline {roof}")
@@ -271,9 +316,11 @@ def main():
                                for k, v in r["prof"].items()}}
     if not args.no_extras:
         log("extras: complex64")
-        r64 = primary(q, W, args.n, q.QSV_C64, max(2, args.steps // 2), 1)
-        extras["c64"] = {"gates_per_s": round(r64["gates"] * max(2, args.steps // 2) / r64["seconds"], 2),
-                         "roofline": kernel_roofline(r64["prof"], "tile_pass_c64")}
+        s64 = max(2, args.steps // 2)
+        r64 = primary(q, W, args.n, q.QSV_C64, s64, 1)
+        extras["c64"] = {"gates_per_s": round(r64["gates"] * s64 / r64["seconds"], 2),
+                         "roofline": kernel_roofline(r64["prof"], "tile_pass_c64", s64,
+                                                     r64["flops_per_step"], "f32")}
         log("extras: unfused sweep")
         extras["unfused_c128"] = unfused_sweep(q, W, args.n)
         log("extras: adjoint ratio")

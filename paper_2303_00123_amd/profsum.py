@@ -24,7 +24,8 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TILE_SOURCES = ["csrc/qsv_tile.hip", "csrc/qsv_plan.cpp", "csrc/qsv_common.h", "csrc/qsv_internal.h"]
+TILE_SOURCES = ["csrc/qsv_tile.hip", "csrc/qsv_tile_core.h", "csrc/qsv_plan.cpp", "csrc/qsv_common.h",
+                "csrc/qsv_internal.h"]
 
 
 def source_hash(files=TILE_SOURCES) -> str:

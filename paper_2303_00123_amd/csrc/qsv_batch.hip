@@ -222,7 +222,7 @@ void mix(uint64_t& h, uint64_t v) {
 std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
                         const double* params, int64_t nparams, const int64_t* term_off,
                         const uint64_t* qmasks, const double* w, int dtype, int K, int L,
-                        BatchBuild& B) {
+                        BatchBuild& B, std::vector<PlanMemo>* memo) {
     const size_t amp = amp_bytes(dtype);
     std::vector<std::vector<Pass>> plans(static_cast<size_t>(nb));
     std::vector<std::vector<PGate>> lowered(static_cast<size_t>(nb));
@@ -259,7 +259,13 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             pg.push_back(p);
         }
         pg = prefuse(pg);
-        plans[size_t(c)] = plan_passes(ne, pg, TileConfig{K, L, K - 8, coal_bits_for(dtype)});
+        const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype)};
+        if (memo) {
+            if (memo->size() < size_t(nb)) memo->resize(size_t(nb));
+            plans[size_t(c)] = plan_memo((*memo)[size_t(c)], ne, pg, bcfg);   // same structure: same plan
+        } else {
+            plans[size_t(c)] = plan_passes(ne, pg, bcfg);
+        }
         // a pass of one gate would run as an unfused kernel in the single-state
         // path; here every pass is a tile pass, so give singletons their stages
         BCirc bc{};
@@ -475,7 +481,7 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
                               int dtype, int K, int L, BatchRun& R, uint64_t& key) {
     BatchBuild B;
     std::string err = build_batch(nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
-                                  K, L, B);
+                                  K, L, B, &ctx->batch_memo);
     if (!err.empty()) {
         ctx->last_error = "qsv_batch_run: " + err;
         return QSV_ERR_ARG;

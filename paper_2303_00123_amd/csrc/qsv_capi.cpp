@@ -457,7 +457,7 @@ static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<
         ctx->cache_n = -1;
         ctx->plan_resident = false;
         ctx->cache_pg = prefuse(pg);
-        ctx->cache_passes = plan_passes(n, ctx->cache_pg, cfg);
+        plan_memo(ctx->memo, n, ctx->cache_pg, cfg);   // replans only if the structure changed
         ctx->cache_in = std::move(pg);
         ctx->cache_n = n;
         ctx->cache_dtype = dtype;
@@ -465,16 +465,16 @@ static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<
     }
     if (log_enabled()) {
         size_t stages = 0, singles = 0;
-        for (const Pass& p : ctx->cache_passes) {
+        for (const Pass& p : ctx->memo.passes) {
             stages += p.stages.size();
             singles += p.single ? 1 : 0;
         }
         logf("apply_circuit: n=%d %zu gates -> %zu after fusion, %zu passes (%zu single-gate), "
              "%zu register stages, tile 2^%d low %d, plan %s",
-             n, ctx->cache_in.size(), ctx->cache_pg.size(), ctx->cache_passes.size(), singles, stages,
+             n, ctx->cache_in.size(), ctx->cache_pg.size(), ctx->memo.passes.size(), singles, stages,
              cfg.tile_bits, cfg.low_bits, hit ? (ctx->plan_resident ? "reused" : "re-uploaded") : "new");
     }
-    return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->cache_passes, true);
+    return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->memo.passes, true);
 }
 
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,

@@ -145,6 +145,16 @@ struct ProfRec {
     hipEvent_t start, stop;
 };
 
+// Pass plan of the last circuit planned through it, keyed by what planning
+// depends on: the qubit count, the tile shape and the positions and kinds of
+// the fused gates (not their matrices).  A circuit evaluated again with new
+// angles keeps its plan; only the device records are rewritten.
+struct PlanMemo {
+    int n = -1;
+    TileConfig cfg{0, 0, 0, 0};
+    std::vector<uint32_t> sig;
+    std::vector<Pass> passes;
+};
 }  // namespace qsv
 
 struct qsv_ctx_s {
@@ -198,8 +208,9 @@ struct qsv_ctx_s {
     int cache_dtype = 0;
     qsv::TileConfig cache_cfg{0, 0, 0, 0};
     std::vector<qsv::PGate> cache_pg;   // fused gates
-    std::vector<qsv::Pass> cache_passes;
-    bool plan_resident = false;         // d_plan holds cache_passes' records
+    qsv::PlanMemo memo;                 // their passes
+    bool plan_resident = false;         // d_plan holds the records of memo.passes
+    std::vector<qsv::PlanMemo> batch_memo;   // per circuit of the last batch
 };
 
 struct qsv_state_s {
@@ -259,8 +270,10 @@ int tile_bits_max(int dtype);
 size_t pass_record_bytes(int dtype, const Pass& ps);
 bool write_pass_record(int dtype, char* dst, const std::vector<PGate>& gates, const Pass& ps);
 
+const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>& fused, const TileConfig& cfg);
+
 // Tile passes: uploads the plan for all passes, then launches them in order.
-// cached: the passes are ctx->cache_passes; their records are uploaded only
+// cached: the passes are ctx->memo.passes; their records are uploaded only
 // if d_plan no longer holds them.
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
                       const std::vector<Pass>& passes, bool cached = false);

@@ -458,4 +458,22 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
     return passes;
 }
 
+const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>& fused, const TileConfig& cfg) {
+    std::vector<uint32_t> sig(fused.size());
+    for (size_t i = 0; i < fused.size(); ++i) {
+        const PGate& g = fused[i];
+        sig[i] = uint32_t(g.kind & 31) | (uint32_t(g.p0 & 63) << 5) |
+                 (uint32_t(is_1q(g.kind) ? 0 : (g.p1 & 63)) << 11) | (uint32_t(g.cs & 1) << 17);
+    }
+    const bool same = m.n == n && m.cfg.tile_bits == cfg.tile_bits && m.cfg.low_bits == cfg.low_bits &&
+                      m.cfg.reg_bits == cfg.reg_bits && m.cfg.coal_bits == cfg.coal_bits && m.sig == sig;
+    if (!same) {
+        m.passes = plan_passes(n, fused, cfg);
+        m.n = n;
+        m.cfg = cfg;
+        m.sig = std::move(sig);
+    }
+    return m.passes;
+}
+
 }  // namespace qsv

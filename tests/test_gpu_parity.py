@@ -176,6 +176,50 @@ def test_tile_shapes_agree(q, ctx, tb, lb):
     c2.close()
 
 
+def permutation_mix(n, ngates, seed):
+    """Random circuit rich in permutation gates (X, CNOT on either control
+    state, SWAP) between Haar gates, so that many register stages end in
+    permutation gates (which the kernels fold into their write offsets)."""
+    rng = np.random.default_rng(seed)
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    SWAP = np.eye(4)[[0, 2, 1, 3]].astype(complex)
+    gates = []
+    for _ in range(ngates):
+        r = rng.random()
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        if r < 0.2:
+            gates.append(W.g1(a, X))
+        elif r < 0.45:
+            gates.append(W.gc(a, b, X, cs=int(rng.integers(2))))
+        elif r < 0.6:
+            gates.append(W.g2(a, b, SWAP))
+        elif r < 0.8:
+            gates.append(W.g1(a, W.haar_unitary(2, rng)))
+        else:
+            gates.append(W.g2(a, b, W.haar_unitary(4, rng)))
+    return W.Circuit(n, gates, name="permutation_mix")
+
+
+@pytest.mark.parametrize("tb,lb,rb", [(12, 3, 4), (11, 3, 3), (10, 3, 2), (12, 3, 3), (13, 3, 5)])
+def test_permutation_gates_at_stage_ends(q, tb, lb, rb):
+    n = 14
+    c = permutation_mix(n, 160, seed=tb * 100 + rb)
+    phi = W.random_state(n, 77)
+    ref = O.run(c, phi)
+    c2 = q.Context()
+    c2.set_tile(q.QSV_C128, tb, lb, rb)
+    c2.set_tile(q.QSV_C64, tb, lb + 1 if lb < 4 else lb, rb)
+    st = make_state(q, c2, n, init=phi)
+    st.apply_circuit(c.gates)
+    assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
+    s64 = make_state(q, c2, n, q.QSV_C64, init=phi.astype(np.complex64))
+    s64.apply_circuit(c.gates)
+    assert infidelity(s64.to_numpy(), ref) <= 1e-6
+    st.free()
+    s64.free()
+    c2.close()
+
+
 def test_layered_brick_and_qft(q, ctx):
     c = W.layered_cnot_brick(16, 4, seed=11)
     st = make_state(q, ctx, 16)

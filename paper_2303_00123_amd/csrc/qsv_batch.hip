@@ -21,11 +21,13 @@
 // (the per-XCD L2s are not coherent with each other) uses agent-scope
 // release/acquire on the per-circuit completion counters.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 
 #include "qsv_tile_core.h"
 
@@ -217,6 +219,69 @@ void mix(uint64_t& h, uint64_t v) {
     }
 }
 
+// f(0 .. n-1) on up to 16 host threads (work handed out one index at a
+// time); serial for small n.  f must not throw.
+template <typename F>
+void parallel_for(int n, F&& f) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nt = std::min(std::min(int(hw ? hw : 1), 16), n);
+    if (nt <= 1 || n < 8) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    };
+    std::vector<std::thread> th;
+    th.reserve(size_t(nt - 1));
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (std::thread& x : th) x.join();
+}
+
+// A pass of one gate (or none) would run as an unfused kernel in the
+// single-state path; here every pass is a tile pass, so give it one register
+// stage holding the gate (between canonical load and store stages when the
+// gate touches a low local bit).
+void make_single_stage(Pass& ps, const std::vector<PGate>& gates, int K) {
+    ps.single = false;
+    ps.stages.clear();
+    ps.rb = K - 8;
+    Stage st;
+    st.nr = K - 8;
+    for (int j = 0; j < st.nr; ++j) st.rbits[j] = 8 + j;
+    uint64_t need = 0;
+    int loc[64];
+    for (int q = 0; q < 64; ++q) loc[q] = -1;
+    for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
+    for (int gi : ps.gates) {
+        const PGate& x = gates[size_t(gi)];
+        need |= uint64_t(1) << loc[x.p0];
+        if (!is_1q(x.kind)) need |= uint64_t(1) << loc[x.p1];
+    }
+    st.gates = ps.gates;
+    if (need & 0xFF) {   // a low local bit: use a register set holding the gate's bits
+        int j = 0;
+        for (int b = 0; b < ps.k && j < st.nr; ++b)
+            if ((need >> b) & 1) st.rbits[j++] = b;
+        for (int b = ps.k - 1; b >= 0 && j < st.nr; --b)
+            if (!((need >> b) & 1)) {
+                need |= uint64_t(1) << b;
+                st.rbits[j++] = b;
+            }
+        std::sort(st.rbits, st.rbits + st.nr);
+        Stage s0, s2;   // canonical load stage and store stage around it
+        s0.nr = s2.nr = st.nr;
+        for (int j2 = 0; j2 < st.nr; ++j2) s0.rbits[j2] = s2.rbits[j2] = 8 + j2;
+        ps.stages.push_back(s0);
+        ps.stages.push_back(st);
+        ps.stages.push_back(s2);
+    } else {
+        ps.stages.push_back(st);
+    }
+}
+
 // Plan every circuit and lay out the device tables.  Returns an error text
 // on invalid input ("" on success).
 std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
@@ -224,34 +289,45 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
                         const uint64_t* qmasks, const double* w, int dtype, int K, int L,
                         BatchBuild& B, std::vector<PlanMemo>* memo) {
     const size_t amp = amp_bytes(dtype);
-    std::vector<std::vector<Pass>> plans(static_cast<size_t>(nb));
+    // per-circuit pass lists: entries of the memo when there is one (reused
+    // in place; the one-gate stage fix-up below is idempotent), else local
+    std::vector<std::vector<Pass>> own(static_cast<size_t>(memo ? 0 : nb));
+    std::vector<std::vector<Pass>*> plans(static_cast<size_t>(nb), nullptr);
+    if (memo && memo->size() < size_t(nb)) memo->resize(size_t(nb));
     std::vector<std::vector<PGate>> lowered(static_cast<size_t>(nb));
     mix(B.shape_key, uint64_t(nb));
     mix(B.shape_key, uint64_t(dtype));
-    int maxp = 0;
-    for (int c = 0; c < nb; ++c) {
+    // per circuit, in parallel: lower, fuse, plan (structure hash per circuit)
+    std::vector<std::string> errs(static_cast<size_t>(nb));
+    std::vector<uint64_t> chash(static_cast<size_t>(nb), 1469598103934665603ull);
+    const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype)};
+    parallel_for(nb, [&](int c) {
         const int n = nq[c];
         const int ne = n < K ? K : n;
         const int64_t g0 = gate_off[c], g1 = gate_off[c + 1];
         std::vector<PGate>& pg = lowered[size_t(c)];
+        pg.reserve(size_t(g1 - g0));
+        uint64_t& h = chash[size_t(c)];
         for (int64_t i = g0; i < g1; ++i) {
             const qsv_gate& G = g[i];
             PGate p{};
-            const std::string at = "circuit " + std::to_string(c) + " gate " + std::to_string(i - g0) + ": ";
+            auto err = [&](const char* what) {
+                errs[size_t(c)] = "circuit " + std::to_string(c) + " gate " + std::to_string(i - g0) + ": " + what;
+            };
             const bool two = G.kind == QSV_GC1Q || G.kind == QSV_G2Q;
-            if (G.kind < QSV_G1Q || G.kind > QSV_GROT) return at + "unknown kind";
+            if (G.kind < QSV_G1Q || G.kind > QSV_GROT) return err("unknown kind");
             if (G.q0 < 0 || G.q0 >= n || (two && (G.q1 < 0 || G.q1 >= n || G.q1 == G.q0)))
-                return at + "bad qubit";
-            mix(B.shape_key, uint64_t(G.kind) | (uint64_t(G.q0) << 8) | (uint64_t(two ? G.q1 : 0) << 16) |
-                                 (uint64_t(G.ctrl_state & 1) << 24) | (uint64_t(G.axis & 3) << 26));
+                return err("bad qubit");
+            mix(h, uint64_t(G.kind) | (uint64_t(G.q0) << 8) | (uint64_t(two ? G.q1 : 0) << 16) |
+                       (uint64_t(G.ctrl_state & 1) << 24) | (uint64_t(G.axis & 3) << 26));
             p.kind = G.kind == QSV_GROT ? QSV_G1Q : G.kind;
             p.p0 = pos_in(ne, G.q0);
             p.p1 = two ? pos_in(ne, G.q1) : 0;
             p.cs = G.ctrl_state;
-            if (G.kind == QSV_GC1Q && G.ctrl_state != 0 && G.ctrl_state != 1) return at + "bad control state";
+            if (G.kind == QSV_GC1Q && G.ctrl_state != 0 && G.ctrl_state != 1) return err("bad control state");
             if (G.kind == QSV_GROT) {
-                if (G.axis < 0 || G.axis > 2) return at + "bad axis";
-                if (G.param < 0 || G.param >= nparams) return at + "parameter index out of range";
+                if (G.axis < 0 || G.axis > 2) return err("bad axis");
+                if (G.param < 0 || G.param >= nparams) return err("parameter index out of range");
                 rotation_matrix(G.axis, params[G.param], p.m);
             } else {
                 std::memcpy(p.m, G.m, sizeof(double) * (G.kind == QSV_G2Q ? 32 : 8));
@@ -259,27 +335,38 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             pg.push_back(p);
         }
         pg = prefuse(pg);
-        const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype)};
         if (memo) {
-            if (memo->size() < size_t(nb)) memo->resize(size_t(nb));
-            plans[size_t(c)] = plan_memo((*memo)[size_t(c)], ne, pg, bcfg);   // same structure: same plan
+            PlanMemo& m = (*memo)[size_t(c)];
+            plan_memo(m, ne, pg, bcfg);   // same structure: same plan
+            plans[size_t(c)] = &m.passes;
         } else {
-            plans[size_t(c)] = plan_passes(ne, pg, bcfg);
+            own[size_t(c)] = plan_passes(ne, pg, bcfg);
+            plans[size_t(c)] = &own[size_t(c)];
         }
-        // a pass of one gate would run as an unfused kernel in the single-state
-        // path; here every pass is a tile pass, so give singletons their stages
-        BCirc bc{};
-        bc.tiles = int32_t(uint64_t(1) << (ne - K));
-        bc.npasses = int32_t(plans[size_t(c)].size());
-        if (bc.npasses == 0) {
+        std::vector<Pass>& pl = *plans[size_t(c)];
+        if (pl.empty()) {
             // no gates: still one (empty) pass to produce the observable
             Pass ps;
             ps.k = K;
             ps.rb = K - 8;
             for (int b = 0; b < K; ++b) ps.pos[b] = b;
-            plans[size_t(c)].push_back(ps);
-            bc.npasses = 1;
+            pl.push_back(ps);
         }
+        // a pass of one gate would run as an unfused kernel in the
+        // single-state path; here every pass is a tile pass
+        for (Pass& ps : pl)
+            if (ps.single || ps.stages.empty()) make_single_stage(ps, pg, K);
+    });
+    for (int c = 0; c < nb; ++c)
+        if (!errs[size_t(c)].empty()) return errs[size_t(c)];
+    for (int c = 0; c < nb; ++c) mix(B.shape_key, chash[size_t(c)]);
+    int maxp = 0;
+    for (int c = 0; c < nb; ++c) {
+        const int n = nq[c];
+        const int ne = n < K ? K : n;
+        BCirc bc{};
+        bc.tiles = int32_t(uint64_t(1) << (ne - K));
+        bc.npasses = int32_t(plans[size_t(c)]->size());
         bc.term_beg = int32_t(B.tmask.size());
         for (int64_t t = term_off[c]; t < term_off[c + 1]; ++t) {
             if (n < 64 && (qmasks[t] >> n)) return "circuit " + std::to_string(c) + ": term names a qubit >= n";
@@ -300,64 +387,36 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
         B.circs.push_back(bc);
         if (bc.npasses > maxp) maxp = bc.npasses;
     }
-    // pass records
-    for (int c = 0; c < nb; ++c) {
-        std::vector<Pass>& pl = plans[size_t(c)];
-        for (size_t p = 0; p < pl.size(); ++p) {
-            Pass& ps = pl[p];
-            if (ps.single || ps.stages.empty()) {
-                // one-gate (or empty) pass: a single canonical stage holding it
-                ps.single = false;
-                ps.stages.clear();
-                ps.rb = K - 8;
-                Stage st;
-                st.nr = K - 8;
-                for (int j = 0; j < st.nr; ++j) st.rbits[j] = 8 + j;
-                // put the gate's bits into the register set if needed
-                uint64_t need = 0;
-                int loc[64];
-                for (int q = 0; q < 64; ++q) loc[q] = -1;
-                for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
-                for (int gi : ps.gates) {
-                    const PGate& x = lowered[size_t(c)][size_t(gi)];
-                    need |= uint64_t(1) << loc[x.p0];
-                    if (!is_1q(x.kind)) need |= uint64_t(1) << loc[x.p1];
-                }
-                if (need & 0xFF) {   // a low local bit: use a register set holding the gate's bits
-                    int j = 0;
-                    for (int b = 0; b < ps.k && j < st.nr; ++b)
-                        if ((need >> b) & 1) st.rbits[j++] = b;
-                    for (int b = ps.k - 1; b >= 0 && j < st.nr; --b)
-                        if (!((need >> b) & 1)) {
-                            need |= uint64_t(1) << b;
-                            st.rbits[j++] = b;
-                        }
-                    std::sort(st.rbits, st.rbits + st.nr);
-                    Stage s0, s2;   // canonical load stage and store stage around it
-                    s0.nr = s2.nr = st.nr;
-                    for (int j2 = 0; j2 < st.nr; ++j2) s0.rbits[j2] = s2.rbits[j2] = 8 + j2;
-                    st.gates = ps.gates;
-                    ps.stages.push_back(s0);
-                    ps.stages.push_back(st);
-                    ps.stages.push_back(s2);
-                } else {
-                    st.gates = ps.gates;
-                    ps.stages.push_back(st);
-                }
+    // pass records: offsets in order, then written in parallel
+    std::vector<size_t> rec_first(static_cast<size_t>(nb) + 1, 0);
+    {
+        size_t total = 0;
+        for (int c = 0; c < nb; ++c) {
+            const std::vector<Pass>& pl = *plans[size_t(c)];
+            rec_first[size_t(c)] = B.passes.size();
+            for (size_t p = 0; p < pl.size(); ++p) {
+                BPass bp{};
+                bp.circ = c;
+                bp.level = int32_t(p);
+                bp.rec_off = uint32_t(total);
+                bp.flags = (p == 0 ? BP_FIRST : 0) | (p + 1 == pl.size() ? BP_LAST : 0);
+                B.passes.push_back(bp);
+                total += pass_record_bytes(dtype, pl[p]);
             }
-            const size_t off = B.plan.size();
-            const size_t bytes = pass_record_bytes(dtype, ps);
-            B.plan.resize(off + bytes, 0);
-            if (!write_pass_record(dtype, B.plan.data() + off, lowered[size_t(c)], ps))
-                return "internal planner error";
-            BPass bp{};
-            bp.circ = c;
-            bp.level = int32_t(p);
-            bp.rec_off = uint32_t(off);
-            bp.flags = (p == 0 ? BP_FIRST : 0) | (p + 1 == pl.size() ? BP_LAST : 0);
-            B.passes.push_back(bp);
         }
+        rec_first[size_t(nb)] = B.passes.size();
+        if (total >= (size_t(1) << 32)) return "batch plan too large";
+        B.plan.assign(total, 0);
     }
+    std::atomic<bool> bad{false};
+    parallel_for(nb, [&](int c) {
+        const std::vector<Pass>& pl = *plans[size_t(c)];
+        for (size_t p = 0; p < pl.size(); ++p) {
+            const size_t off = B.passes[rec_first[size_t(c)] + p].rec_off;
+            if (!write_pass_record(dtype, B.plan.data() + off, lowered[size_t(c)], pl[p])) bad = true;
+        }
+    });
+    if (bad) return "internal planner error";
     if (B.plan.size() >= (size_t(1) << 32)) return "batch plan too large";
     // items, pass-level-major; within a level, larger circuits first
     std::vector<int> pass_first(static_cast<size_t>(nb), 0);

@@ -253,16 +253,21 @@ qsv_status qsv_profile_begin(qsv_ctx ctx);
 qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
 
 /* Tile shape of the context's later fused passes for one dtype.
- * tile_bits: log2 of the amplitudes per tile, in [10, 13] (0 = the default, 12).
+ * tile_bits: log2 of the amplitudes per tile, in [10, 13] (0 = the default, 13).
  * low_bits: number of lowest index bits every tile keeps, so each tile is
  * made of contiguous runs of 2^low_bits amplitudes; in [0, tile_bits - 2]
  * (0 = 3 for QSV_C128, 4 for QSV_C64, i.e. 128-byte runs).
  * reg_bits: log2 of the amplitudes each thread keeps in registers (a tile
- * has 2^(tile_bits - reg_bits) threads; 0 = 4 for tiles of 2^12 or more,
- * else tile_bits - 8).  Compiled (tile_bits, reg_bits) shapes: (10, 2),
+ * has 2^(tile_bits - reg_bits) threads; 0 = 5 for tiles of 2^13, 4 for
+ * 2^12, else tile_bits - 8).  Compiled (tile_bits, reg_bits) shapes: (10, 2),
  * (11, 3), (12, 3), (12, 4), (13, 4), (13, 5); others give QSV_ERR_ARG.
+ * lds_rounds: how a tile changes register mapping between stages: 1 = the
+ * whole tile goes through LDS at once; 2 = consecutive stages share a
+ * register bit and the tile moves in two halves, so a workgroup needs half
+ * the LDS and more workgroups fit on a compute unit (0 = 2).
  * States with fewer than 10 qubits run one kernel per gate. */
-qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits);
+qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits,
+                        int lds_rounds);
 
 /* Host-only query of the exact gate sequence the tile kernels would apply for
  * qsv_apply_circuit (no device work; needs no GPU): gates grouped into passes

@@ -660,12 +660,13 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
 }
 
 // ------------------------------------------------------------------ tuning
-static qsv_status tile_config(int dtype, int tile_bits, int low_bits, int reg_bits, TileConfig& out,
-                              std::string& err) {
+static qsv_status tile_config(int dtype, int tile_bits, int low_bits, int reg_bits, int lds_rounds,
+                              TileConfig& out, std::string& err) {
     const int kmax = tile_bits_max(dtype);
     const int tb = tile_bits ? tile_bits : kDefaultTileBits;
     const int lb = low_bits ? low_bits : (dtype == QSV_C128 ? 3 : 4);
-    const int rb = reg_bits ? reg_bits : (tb >= 12 ? kDefaultRegBits : tb - 8);
+    // default register bits: 5 for 2^13-amplitude tiles, 4 for 2^12, else tile_bits - 8
+    const int rb = reg_bits ? reg_bits : (tb >= 13 ? kDefaultRegBits : tb == 12 ? 4 : tb - 8);
     if (tb < kMinTileBits || tb > kmax) {
         err = "tile_bits must be in [" + std::to_string(kMinTileBits) + ", " + std::to_string(kmax) + "]";
         return QSV_ERR_ARG;
@@ -678,16 +679,22 @@ static qsv_status tile_config(int dtype, int tile_bits, int low_bits, int reg_bi
         err = "no tile kernel for tile_bits " + std::to_string(tb) + " with reg_bits " + std::to_string(rb);
         return QSV_ERR_ARG;
     }
-    out = TileConfig{tb, lb, rb, coal_bits_for(dtype)};
+    if (lds_rounds < 0 || lds_rounds > 2) {
+        err = "lds_rounds must be 0, 1 or 2";
+        return QSV_ERR_ARG;
+    }
+    out = TileConfig{tb, lb, rb, coal_bits_for(dtype), lds_rounds == 1 ? 0 : 1};
     return QSV_OK;
 }
 
-qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits) {
+qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits,
+                        int lds_rounds) {
     if (!ctx) return QSV_ERR_ARG;
     if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
     std::string err;
     TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return fail(ctx, s, err);
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err))
+        return fail(ctx, s, err);
     (dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64) = cfg;
     return QSV_OK;
 }
@@ -701,7 +708,7 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
         return QSV_ERR_ARG;
     std::string err;
     TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return s;
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, 0, cfg, err)) return s;
     // positions only: rotations get a placeholder angle
     std::vector<double> zeros(size_t(ng) + 1, 0.0);
     std::vector<qsv_gate> gg(g, g + ng);
@@ -735,7 +742,7 @@ qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const
     if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
     std::string err;
     TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, cfg, err)) return s;
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, 0, cfg, err)) return s;
     std::vector<PGate> pg;
     if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
     if (n >= kMinTileBits) pg = prefuse(pg);

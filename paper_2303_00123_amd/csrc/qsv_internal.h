@@ -40,6 +40,8 @@ inline int coal_bits_for(int dtype) { return dtype == QSV_C128 ? 3 : 4; }
 struct Stage {
     int nr = 0;                  // register bits of the pass's kernel
     int rbits[8] = {0};          // register bit j <-> local tile bit rbits[j]
+    int hprev = -1;              // split exchange: local bit shared with the previous stage
+                                 // (it is rbits[nr - 1]); -1 for the first stage
     std::vector<int> gates;      // indices into the lowered gate list, in execution order
 };
 
@@ -49,6 +51,8 @@ struct Pass {
     int k = 0;                   // tile bits (tile = 2^k amplitudes)
     int rb = 0;                  // register bits per thread (2^(k - rb) threads)
     int coal = 0;                // local bits the first/last stage keep on lanes
+    bool split = false;          // stage changes go through half the tile in LDS, in two
+                                 // rounds split on a register bit shared by both stages
     int pos[24] = {0};           // ascending global bit positions of the tile's local bits
     std::vector<int> gates;      // indices into the lowered gate list, in execution order
     std::vector<Stage> stages;   // stage 0 and the last stage use the canonical mapping
@@ -60,12 +64,13 @@ struct TileConfig {
     int reg_bits;    // log2 amplitudes per thread (threads per tile = 2^(tile_bits - reg_bits))
     int coal_bits;   // the first and last stage keep local bits [0, coal_bits) on lanes, so
                      // global loads and stores move 2^coal_bits contiguous amplitudes per lane group
+    int split = 0;   // 1: split stage changes (half the tile in LDS, see Pass::split)
 };
 
 constexpr int kTileThreads = 256;   // threads per workgroup of the batch and adjoint kernels
 constexpr int kMinTileBits = 10;    // at least 2 register bits per thread
-constexpr int kDefaultTileBits = 12;
-constexpr int kDefaultRegBits = 4;
+constexpr int kDefaultTileBits = 13;   // 2^13 amplitudes, 32 per thread, split LDS exchange
+constexpr int kDefaultRegBits = 5;
 
 // (tile_bits, reg_bits) pairs the single-state tile kernel is compiled for
 bool tile_shape_supported(int dtype, int tile_bits, int reg_bits);
@@ -112,6 +117,12 @@ struct TStage {
     uint32_t su[32];        // byte offset (after the LDS swizzle) of register slot u (reads)
     uint32_t su_wr[32];     // the same for the write at the stage's end: su of the slot the
                             // amplitude belongs to after the stage's trailing permutation gates
+    // split exchange (half the tile in LDS): the bit shared with the previous
+    // stage is removed from the read addresses, the one shared with the next
+    // stage from the write addresses (su and su_wr are then half-tile offsets)
+    int32_t jw;             // register index of the bit shared with the next stage (-1: none)
+    int32_t tbr[10];        // thread bit j -> half-tile address bit, reads
+    int32_t tbw[10];        // thread bit j -> half-tile address bit, writes
 };
 
 // Pass header in device memory; followed by nstages TStage records and then
@@ -176,8 +187,8 @@ struct qsv_ctx_s {
     double* d_aux = nullptr;
     size_t d_aux_doubles = 0;
 
-    qsv::TileConfig tile_c128{12, 3, 4, 3};
-    qsv::TileConfig tile_c64{12, 4, 4, 4};
+    qsv::TileConfig tile_c128{13, 3, 5, 3, 1};
+    qsv::TileConfig tile_c64{13, 4, 5, 4, 1};
 
     // profiling
     bool profiling = false;

@@ -123,6 +123,7 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     const int K = ps.k;
     const int RB = ps.rb;
     const int C = std::min(ps.coal, K - RB);
+    const bool split = ps.split;
     int loc[64];
     for (int p = 0; p < 64; ++p) loc[p] = -1;
     for (int b = 0; b < K; ++b) loc[ps.pos[b]] = b;
@@ -135,16 +136,32 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         lm[size_t(gi)] = m;
     }
     const uint64_t lanes = (uint64_t(1) << C) - 1;   // bits the first/last stage keep on lanes
-    // a register set of RB bits containing S; padding prefers the highest free
-    // bits, and never the lane bits when `avoid` is set
-    auto make_stage = [&](uint64_t S, bool avoid, std::vector<int>&& g) {
+    auto mask_of = [&](const Stage& st) {
+        uint64_t m = 0;
+        for (int j = 0; j < st.nr; ++j) m |= uint64_t(1) << st.rbits[j];
+        return m;
+    };
+    // A register set of RB bits containing S; padding prefers the highest
+    // free bits, and never the lane bits when `avoid` is set.  With a split
+    // exchange the set shares a bit h with `prev` (the previous stage's
+    // set), which goes last in the register order.
+    auto make_stage = [&](uint64_t S, bool avoid, uint64_t prev, std::vector<int>&& g) {
         Stage st;
         st.nr = RB;
+        int h = -1;
+        if (split && prev) {
+            const uint64_t common = S & prev;
+            const uint64_t cand = common ? common : (prev & ~(avoid ? lanes : 0));
+            if (cand) h = 63 - __builtin_clzll(cand);   // highest candidate
+            if (h >= 0) S |= uint64_t(1) << h;
+        }
         for (int b = K - 1; b >= 0 && __builtin_popcountll(S) < RB; --b)
             if (!((S >> b) & 1) && !(avoid && ((lanes >> b) & 1))) S |= uint64_t(1) << b;
         int j = 0;
         for (int b = 0; b < K && j < RB; ++b)
-            if ((S >> b) & 1) st.rbits[j++] = b;
+            if (((S >> b) & 1) && b != h) st.rbits[j++] = b;
+        if (h >= 0) st.rbits[j++] = h;
+        st.hprev = h;
         st.gates = std::move(g);
         return st;
     };
@@ -174,23 +191,39 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
     std::vector<int> rem = ps.gates, take, defer;
     uint64_t S = 0;
     greedy_avoid(rem, S, take, defer);
-    ps.stages.push_back(make_stage(S, true, std::move(take)));
+    ps.stages.push_back(make_stage(S, true, 0, std::move(take)));
     rem.swap(defer);
     while (!rem.empty()) {
+        const uint64_t prev = mask_of(ps.stages.back());
         take.clear();
         defer.clear();
         S = 0;
         greedy(rem, lm, S, RB, false, take, defer);
+        if (split && !(S & prev) && __builtin_popcountll(S) == RB) {
+            // leave room for a bit shared with the previous stage
+            take.clear();
+            defer.clear();
+            S = 0;
+            greedy(rem, lm, S, RB - 1, false, take, defer);
+        }
         uint64_t used = 0;
         for (int gi : take) used |= lm[size_t(gi)];
         // a stage that avoids the lane bits can also be the store stage
-        ps.stages.push_back(make_stage(S, (used & lanes) == 0, std::move(take)));
+        bool avoid = (used & lanes) == 0;
+        if (avoid && split && !(S & prev) && !(prev & ~lanes)) avoid = false;   // shared bit is a lane bit
+        ps.stages.push_back(make_stage(S, avoid, prev, std::move(take)));
         rem.swap(defer);
     }
     // the store needs a stage that keeps the lane bits on lanes
-    uint64_t lastreg = 0;
-    for (int j = 0; j < ps.stages.back().nr; ++j) lastreg |= uint64_t(1) << ps.stages.back().rbits[j];
-    if (lastreg & lanes) ps.stages.push_back(make_stage(0, true, {}));
+    if (mask_of(ps.stages.back()) & lanes) {
+        uint64_t prev = mask_of(ps.stages.back());
+        if (split && !(prev & ~lanes)) {
+            // no bit to share that is off the lanes: an empty stage in between
+            ps.stages.push_back(make_stage(0, false, prev, {}));
+            prev = mask_of(ps.stages.back());
+        }
+        ps.stages.push_back(make_stage(0, true, prev, {}));
+    }
 }
 
 // ------------------------------------------------------------ stage fusion
@@ -447,6 +480,8 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
         ps.k = K;
         ps.rb = tile_shape_supported(QSV_C128, K, cfg.reg_bits) ? cfg.reg_bits : K - 8;
         ps.coal = cfg.coal_bits;
+        // a shared register bit leaves RB - 1 >= 2 bits for a 2-qubit gate
+        ps.split = cfg.split != 0 && ps.rb >= 3;
         int i = 0;
         for (int p = 0; p < n; ++p)
             if ((S >> p) & 1) ps.pos[i++] = p;

@@ -31,11 +31,11 @@ using namespace tile;
 // One workgroup per tile.  Every stage record (including the first and the
 // last, which carry the load mapping) drives the same loop body, so the gate
 // dispatch is compiled once.  Slot offsets come precomputed in the plan.
-template <typename R, int K, int RB>
+template <typename R, int K, int RB, bool SPLIT>
 __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* __restrict__ s,
                                                         const char* __restrict__ plan) {
     using V = typename V2T<R>::type;
-    constexpr int E = 1 << K;
+    constexpr int E = SPLIT ? 1 << (K - 1) : 1 << K;   // LDS amplitudes
     constexpr int TB = K - RB;
     constexpr int P = 1 << RB;
     __shared__ V tile[E];
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
     V v[P];
 #pragma unroll
     for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
-    run_stages<R, K, RB>(v, lds, stg, nst, gates, tid);
+    run_stages<R, K, RB, SPLIT>(v, lds, stg, nst, gates, tid);
     V* const sq = s + (b | deposit(tid, hdr->tpos_st, TB));
 #pragma unroll
     for (int u = 0; u < P; ++u) sq[hdr->du_st[u]] = v[u];
@@ -146,11 +146,15 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
 }
 
 template <typename R, int K, int RB>
-hipError_t launch_tile(qsv_ctx ctx, void* s, int n, const char* dplan) {
+hipError_t launch_tile(qsv_ctx ctx, void* s, int n, bool split, const char* dplan) {
     using V = typename V2T<R>::type;
     const unsigned tiles = unsigned(uint64_t(1) << (n - K));
-    hipLaunchKernelGGL((k_tile<R, K, RB>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
-                       static_cast<V*>(s), dplan);
+    if (split)
+        hipLaunchKernelGGL((k_tile<R, K, RB, true>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
+                           static_cast<V*>(s), dplan);
+    else
+        hipLaunchKernelGGL((k_tile<R, K, RB, false>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
+                           static_cast<V*>(s), dplan);
     return hipGetLastError();
 }
 
@@ -158,14 +162,14 @@ hipError_t launch_tile(qsv_ctx ctx, void* s, int n, const char* dplan) {
 // tile size, plus 512-thread variants (more waves per SIMD) at 2^12 and 2^13
 // and 2^13-amplitude tiles with 32 amplitudes per thread.
 template <typename R>
-hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, const char* dplan) {
+hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, bool split, const char* dplan) {
     switch (k * 8 + rb) {
-    case 10 * 8 + 2: return launch_tile<R, 10, 2>(ctx, s, n, dplan);
-    case 11 * 8 + 3: return launch_tile<R, 11, 3>(ctx, s, n, dplan);
-    case 12 * 8 + 3: return launch_tile<R, 12, 3>(ctx, s, n, dplan);
-    case 12 * 8 + 4: return launch_tile<R, 12, 4>(ctx, s, n, dplan);
-    case 13 * 8 + 4: return launch_tile<R, 13, 4>(ctx, s, n, dplan);
-    case 13 * 8 + 5: return launch_tile<R, 13, 5>(ctx, s, n, dplan);
+    case 10 * 8 + 2: return launch_tile<R, 10, 2>(ctx, s, n, split, dplan);
+    case 11 * 8 + 3: return launch_tile<R, 11, 3>(ctx, s, n, split, dplan);
+    case 12 * 8 + 3: return launch_tile<R, 12, 3>(ctx, s, n, split, dplan);
+    case 12 * 8 + 4: return launch_tile<R, 12, 4>(ctx, s, n, split, dplan);
+    case 13 * 8 + 4: return launch_tile<R, 13, 4>(ctx, s, n, split, dplan);
+    case 13 * 8 + 5: return launch_tile<R, 13, 5>(ctx, s, n, split, dplan);
     default: return hipErrorInvalidValue;
     }
 }
@@ -254,6 +258,13 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
         std::vector<PGate> fused = fuse_stage(gates, st.gates);
         std::vector<char> virt(fused.size(), 0);
         uint32_t touched = 0;   // register bits used by later gates that run
+        // split exchange: the bit shared with the next stage decides the write
+        // round, so no permutation may move it
+        const int hnext = (ps.split && si + 1 < ns) ? ps.stages[size_t(si) + 1].hprev : -1;
+        if (hnext >= 0) {
+            if (reg[hnext] < 0) return false;
+            touched |= 1u << reg[hnext];
+        }
         for (size_t i = fused.size(); i-- > 0;) {
             const PGate& fg = fused[i];
             const int b0 = loc[fg.p0] >= 0 ? reg[loc[fg.p0]] : -1;
@@ -325,16 +336,33 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
         for (int b = 0; b < ps.k && tj < 10; ++b)
             if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
         for (; tj < 10; ++tj) ts[si].tbits[tj] = 0;
-        auto slot_off = [&](int u) {
+        // split exchange: half-tile addresses without the shared bit
+        const int hprev = ps.split ? st.hprev : -1;
+        const int hnext = (ps.split && si + 1 < ns) ? ps.stages[size_t(si) + 1].hprev : -1;
+        if (ps.split && si > 0 && (hprev < 0 || st.rbits[st.nr - 1] != hprev)) return false;
+        auto drop = [](uint32_t e, int h) {   // remove local bit h from e
+            return h < 0 ? e : ((e & ((1u << h) - 1)) | ((e >> (h + 1)) << h));
+        };
+        auto slot_off_h = [&](int u, int h) {
             uint32_t e = 0;
             for (int j = 0; j < st.nr; ++j)
                 if ((u >> j) & 1) e |= 1u << st.rbits[j];
-            return tile_swz(e, int(sizeof(V))) * uint32_t(sizeof(V));
+            return tile_swz(drop(e, h), int(sizeof(V))) * uint32_t(sizeof(V));
         };
         for (int u = 0; u < 32; ++u) {
             const bool in = u < (1 << st.nr);
-            ts[si].su[u] = in ? slot_off(u) : 0;
-            ts[si].su_wr[u] = in ? slot_off(dest[size_t(si)][u]) : 0;
+            ts[si].su[u] = in ? slot_off_h(u, hprev) : 0;
+            ts[si].su_wr[u] = in ? slot_off_h(dest[size_t(si)][u], hnext) : 0;
+        }
+        ts[si].jw = -1;
+        if (hnext >= 0)
+            for (int j = 0; j < st.nr; ++j)
+                if (st.rbits[j] == hnext) ts[si].jw = j;
+        if (hnext >= 0 && ts[si].jw < 0) return false;
+        for (int j = 0; j < 10; ++j) {
+            const int b = ts[si].tbits[j];
+            ts[si].tbr[j] = (hprev >= 0 && b > hprev) ? b - 1 : b;
+            ts[si].tbw[j] = (hnext >= 0 && b > hnext) ? b - 1 : b;
         }
         for (const PGate& fg : run[size_t(si)])
             if (!to_device_gate<R>(fg, loc, st, tg[gi++])) return false;
@@ -384,7 +412,7 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
             e = launch_gate(ctx, s, n, dt, gates[size_t(ps.gates[0])]);
         } else {
             prof_before(ctx, pname, 2.0 * double(uint64_t(1) << n) * sizeof(V));
-            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, dev + offs[i]);
+            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, ps.split, dev + offs[i]);
             prof_after(ctx);
         }
         if (e != hipSuccess) return e;

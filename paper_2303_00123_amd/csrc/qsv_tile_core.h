@@ -211,29 +211,71 @@ __device__ __forceinline__ void apply_range(V (&v)[P], const TGate<R>* __restric
     }
 }
 
+// Write the register slots u whose register bit J equals RHO to LDS.
+template <int RB, int RHO, typename V>
+__device__ __forceinline__ void write_half(const V (&v)[1 << RB], char* lds, uint32_t sb,
+                                           const uint32_t* su, int jw) {
+    on_bit<RB>(jw, [&](auto J) __attribute__((always_inline)) {
+        constexpr int j = decltype(J)::value;
+#pragma unroll
+        for (int u = 0; u < (1 << RB); ++u)
+            if (((u >> j) & 1) == RHO) *reinterpret_cast<V*>(lds + (sb ^ su[u])) = v[u];
+    });
+}
+
 // Run stages of a pass on the register-resident amplitudes v: stage 0 and
-// the last stage use the load mapping; stages in between re-map through LDS.
+// the last stage use the load and store mappings; stages in between re-map
+// through LDS.  Full exchange (SPLIT false): the whole tile is written, then
+// read back in the next stage's mapping.  Split exchange: consecutive stages
+// share a register bit h (the next stage's last register bit), and the tile
+// moves in two rounds through half of it in LDS -- the amplitudes with h = 0,
+// then those with h = 1 -- so a workgroup needs half the LDS.
 // Ends with every thread done reading LDS if the pass used it (the caller
 // may reuse `lds` right away only after its own barrier).
-template <typename R, int K, int RB, typename V>
+template <typename R, int K, int RB, bool SPLIT = false, typename V>
 __device__ __forceinline__ void run_stages(V (&v)[1 << RB], char* lds, const TStage* stg,
                                            int nst, const TGate<R>* gates, uint32_t tid) {
     constexpr int TB = K - RB;
     constexpr int P = 1 << RB;
     constexpr uint32_t ES = sizeof(V);
-    for (int st = 0; st < nst; ++st) {
-        const TStage& S = stg[st];
-        // LDS byte address of slot u = swz(eb | du) * ES = swz(eb) * ES ^ su[u]
-        const uint32_t sb = swz<R>(deposit32(tid, S.tbits, TB)) * ES;
-        if (st > 0) {
+    if constexpr (!SPLIT) {
+        for (int st = 0; st < nst; ++st) {
+            const TStage& S = stg[st];
+            // LDS byte address of slot u = swz(eb | du) * ES = swz(eb) * ES ^ su[u]
+            const uint32_t sb = swz<R>(deposit32(tid, S.tbits, TB)) * ES;
+            if (st > 0) {
 #pragma unroll
-            for (int u = 0; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sb ^ S.su[u]));
+                for (int u = 0; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sb ^ S.su[u]));
+            }
+            apply_range<RB>(v, gates, S.gbeg, S.gend);
+            if (st < nst - 1) {
+#pragma unroll
+                for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su_wr[u])) = v[u];
+                lds_barrier();
+            }
         }
-        apply_range<RB>(v, gates, S.gbeg, S.gend);
-        if (st < nst - 1) {
+    } else {
+        for (int st = 0; st < nst; ++st) {
+            const TStage& S = stg[st];
+            apply_range<RB>(v, gates, S.gbeg, S.gend);
+            if (st + 1 < nst) {
+                const TStage& N = stg[st + 1];
+                const uint32_t sbw = swz<R>(deposit32(tid, S.tbw, TB)) * ES;
+                const uint32_t sbr = swz<R>(deposit32(tid, N.tbr, TB)) * ES;
+                V w[P / 2];
+                if (st > 0) lds_barrier();   // the previous change's reads are done
+                write_half<RB, 0>(v, lds, sbw, S.su_wr, S.jw);
+                lds_barrier();
 #pragma unroll
-            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(lds + (sb ^ S.su_wr[u])) = v[u];
-            lds_barrier();
+                for (int u = 0; u < P / 2; ++u) w[u] = *reinterpret_cast<const V*>(lds + (sbr ^ N.su[u]));
+                lds_barrier();
+                write_half<RB, 1>(v, lds, sbw, S.su_wr, S.jw);
+                lds_barrier();
+#pragma unroll
+                for (int u = P / 2; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sbr ^ N.su[u]));
+#pragma unroll
+                for (int u = 0; u < P / 2; ++u) v[u] = w[u];
+            }
         }
     }
 }

@@ -94,7 +94,7 @@ def lib():
         "qsv_batch_run": [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, i32, vp, i32],
         "qsv_profile_begin": [vp],
         "qsv_profile_end": [vp, vp, i32, P(i32)],
-        "qsv_set_tile": [vp, i32, i32, i32, i32],
+        "qsv_set_tile": [vp, i32, i32, i32, i32, i32],
         "qsv_plan_circuit": [i32, i32, vp, i64, i32, i32, i32, P(i64), vp, vp, vp],
         "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, i32, vp, i64, vp, P(i64)],
     }
@@ -179,8 +179,9 @@ class Context:
     def sync(self):
         self.check(lib().qsv_sync(self.handle))
 
-    def set_tile(self, dtype: int, tile_bits: int = 0, low_bits: int = 0, reg_bits: int = 0):
-        self.check(lib().qsv_set_tile(self.handle, dtype, tile_bits, low_bits, reg_bits))
+    def set_tile(self, dtype: int, tile_bits: int = 0, low_bits: int = 0, reg_bits: int = 0,
+                 lds_rounds: int = 0):
+        self.check(lib().qsv_set_tile(self.handle, dtype, tile_bits, low_bits, reg_bits, lds_rounds))
 
     def profile_begin(self):
         self.check(lib().qsv_profile_begin(self.handle))

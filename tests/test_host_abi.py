@@ -77,7 +77,7 @@ def _check_plan(c, tile_bits, low_bits, dtype=q.QSV_C128):
     assert sorted(order.tolist()) == list(range(ng))
     # passes are executed in order
     assert np.all(np.diff(pog[order]) >= 0)
-    kbits = min(tile_bits or 12, c.n)
+    kbits = min(tile_bits or 13, c.n)   # library default: 2^13-amplitude tiles
     lbits = min(low_bits or 3, kbits)
     for p, mask in enumerate(pq):
         mask = int(mask)

@@ -130,11 +130,29 @@ __device__ __forceinline__ void apply_gate2(const V (&sv)[P], V (&dv)[P], const 
         double part = 0.0;
         on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) {
             constexpr int b = decltype(B)::value;
-            if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(sv, sl);
-            else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(sv, sl);
-            else part = rot_part<b, QSV_AXIS_Z>(sv, sl);
-            rg_1q<b>(sv, dv, g.m);
-            rg_1q<b>(sl, dl, g.m);
+            // the rewind exp(+i theta P / 2) has the structure of its axis:
+            // X -> [[c, i s], [i s, c]], Y -> real, Z -> diagonal.  The
+            // complex64 kernel keeps the generic body: the three specialised
+            // ones push it past 256 registers (one wave per SIMD).
+            if constexpr (sizeof(R) == 4) {
+                if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(sv, sl);
+                else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(sv, sl);
+                else part = rot_part<b, QSV_AXIS_Z>(sv, sl);
+                rg_1q<b>(sv, dv, g.m);
+                rg_1q<b>(sl, dl, g.m);
+            } else if (g.cs == QSV_AXIS_X) {
+                part = rot_part<b, QSV_AXIS_X>(sv, sl);
+                rg_1x<b>(sv, dv, g.m);
+                rg_1x<b>(sl, dl, g.m);
+            } else if (g.cs == QSV_AXIS_Y) {
+                part = rot_part<b, QSV_AXIS_Y>(sv, sl);
+                rg_1r<b>(sv, dv, g.m);
+                rg_1r<b>(sl, dl, g.m);
+            } else {
+                part = rot_part<b, QSV_AXIS_Z>(sv, sl);
+                rg_1d<b>(sv, dv, g.m + 8);
+                rg_1d<b>(sl, dl, g.m + 8);
+            }
         });
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if ((tid & 63) == 0) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
@@ -147,13 +165,16 @@ __device__ __forceinline__ void apply_gate2(const V (&sv)[P], V (&dv)[P], const 
 
 // One two-vector tile pass.  partials: this pass's block of
 // [tile][slot][wave] doubles (slot count in the header's pad field).
-template <typename R, int K>
+// SPLIT: consecutive stages share a register bit and each vector changes
+// mapping in two half-tile rounds through LDS (see run_stages), so the two
+// tiles take half the LDS.
+template <typename R, int K, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __restrict__ psi,
                                                        typename V2T<R>::type* __restrict__ lam,
                                                        const char* __restrict__ plan,
                                                        double* __restrict__ partials) {
     using V = typename V2T<R>::type;
-    constexpr int E = 1 << K;
+    constexpr int E = SPLIT ? 1 << (K - 1) : 1 << K;   // LDS amplitudes per vector
     constexpr int RB = K - 8;
     constexpr int P = 1 << RB;
     constexpr uint32_t ES = sizeof(V);
@@ -186,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     for (int st = 0; st < nst; ++st) {
         const TStage& S = stg[st];
         const uint32_t sb = swz<R>(deposit32(tid, S.tbits, 8)) * ES;
-        if (st > 0) {
+        if (!SPLIT && st > 0) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
                 v[u] = *reinterpret_cast<const V*>(lp + (sb ^ S.su[u]));
@@ -202,13 +223,42 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
                 apply_gate2<RB>(vw, v, lw, l, gates[two ? g + 1 : g], !two, part_out, tid);
             }
         }
-        if (st < nst - 1) {
+        if (!SPLIT && st < nst - 1) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
                 *reinterpret_cast<V*>(lp + (sb ^ S.su_wr[u])) = v[u];
                 *reinterpret_cast<V*>(ll + (sb ^ S.su_wr[u])) = l[u];
             }
             lds_barrier();
+        }
+        if (SPLIT && st < nst - 1) {
+            const TStage& N = stg[st + 1];
+            const uint32_t sbw = swz<R>(deposit32(tid, S.tbw, 8)) * ES;
+            const uint32_t sbr = swz<R>(deposit32(tid, N.tbr, 8)) * ES;
+            V wv[P / 2], wl[P / 2];
+            if (st > 0) lds_barrier();   // the previous change's reads are done
+            write_half<RB, 0>(v, lp, sbw, S.su_wr, S.jw);
+            write_half<RB, 0>(l, ll, sbw, S.su_wr, S.jw);
+            lds_barrier();
+#pragma unroll
+            for (int u = 0; u < P / 2; ++u) {
+                wv[u] = *reinterpret_cast<const V*>(lp + (sbr ^ N.su[u]));
+                wl[u] = *reinterpret_cast<const V*>(ll + (sbr ^ N.su[u]));
+            }
+            lds_barrier();
+            write_half<RB, 1>(v, lp, sbw, S.su_wr, S.jw);
+            write_half<RB, 1>(l, ll, sbw, S.su_wr, S.jw);
+            lds_barrier();
+#pragma unroll
+            for (int u = P / 2; u < P; ++u) {
+                v[u] = *reinterpret_cast<const V*>(lp + (sbr ^ N.su[u]));
+                l[u] = *reinterpret_cast<const V*>(ll + (sbr ^ N.su[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < P / 2; ++u) {
+                v[u] = wv[u];
+                l[u] = wl[u];
+            }
         }
     }
     const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);
@@ -244,7 +294,7 @@ hipError_t launch_adj_tile(qsv_ctx ctx, void* psi, void* lam, int n, const char*
                            double* partials) {
     using V = typename V2T<R>::type;
     const unsigned tiles = unsigned(uint64_t(1) << (n - K));
-    hipLaunchKernelGGL((k_adj_tile<R, K>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
+    hipLaunchKernelGGL((k_adj_tile<R, K, false>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
                        static_cast<V*>(psi), static_cast<V*>(lam), rec, partials);
     return hipGetLastError();
 }
@@ -365,7 +415,8 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
             rev.push_back(d);
         }
         rev = prefuse(rev);
-        std::vector<Pass> passes = plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt)});
+        std::vector<Pass> passes =
+            plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt), 0});
         // slots, record layout, partial-buffer size
         size_t bytes = 0, max_part = 0;
         std::vector<size_t> offs(passes.size(), 0), tag_off(passes.size(), 0);

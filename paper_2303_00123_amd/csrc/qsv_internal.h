@@ -98,7 +98,8 @@ enum {
     DK_CX = 3,    // swap on r1 where r0 == cs (controlled X)
     DK_CD = 4,    // diagonal (d0, d1) on r1 where r0 == cs
     DK_2Q = 5,    // generic 4x4 on (r0, r1), local index 2*x_r0 + x_r1
-    DK_ROT = 6    // adjoint sweep: partial Im<lam|P|psi> into slot r1, then 2x2 m on r0; P = axis cs
+    DK_ROT = 6,   // adjoint sweep: partial Im<lam|P|psi> into slot r1, then 2x2 m on r0; P = axis cs
+    DK_1R = 8     // real 2x2 on register bit r0 (m[0], m[2], m[4], m[6]; imaginary parts zero)
 };
 
 // Device-side gate record of a tile pass (register bit coordinates).

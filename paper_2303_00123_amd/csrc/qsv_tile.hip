@@ -86,6 +86,8 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
         t.r1 = g.p1;    // partial-sum slot
         t.cs = g.cs;    // axis
         for (int i = 0; i < 8; ++i) t.m[i] = R(g.m[i]);
+        // the diagonal (d0, d1) again at m[8..11], for the axis-Z body
+        t.m[8] = R(g.m[0]); t.m[9] = R(g.m[1]); t.m[10] = R(g.m[6]); t.m[11] = R(g.m[7]);
         return true;
     }
     const double* m = g.m;
@@ -108,6 +110,9 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
         if (is_zero(m[2]) && is_zero(m[3]) && is_zero(m[4]) && is_zero(m[5])) {
             t.kind = DK_1D;
             t.m[0] = R(m[0]); t.m[1] = R(m[1]); t.m[2] = R(m[6]); t.m[3] = R(m[7]);
+        } else if (is_zero(m[1]) && is_zero(m[3]) && is_zero(m[5]) && is_zero(m[7])) {
+            t.kind = DK_1R;
+            for (int i = 0; i < 8; ++i) t.m[i] = R(m[i]);
         } else {
             t.kind = DK_1Q;
             for (int i = 0; i < 8; ++i) t.m[i] = R(m[i]);

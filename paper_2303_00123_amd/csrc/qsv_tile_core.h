@@ -63,6 +63,41 @@ __device__ __forceinline__ void rg_1q(const V (&s)[P], V (&d)[P], const R* m) {
         if (!(i & (1 << B))) mv2(m, s[i], s[i | (1 << B)], d[i], d[i | (1 << B)]);
 }
 
+// Real 2x2 (rotations about Y, Hadamard): four real multiply-adds per pair
+// component instead of eight complex ones.
+template <int B, typename R, typename V, int P>
+__device__ __forceinline__ void rg_1r(const V (&s)[P], V (&d)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!(i & (1 << B))) {
+            const V a = s[i], b = s[i | (1 << B)];
+            V x, y;
+            x.x = fmaR(m[2], b.x, m[0] * a.x);
+            x.y = fmaR(m[2], b.y, m[0] * a.y);
+            y.x = fmaR(m[6], b.x, m[4] * a.x);
+            y.y = fmaR(m[6], b.y, m[4] * a.y);
+            d[i] = x;
+            d[i | (1 << B)] = y;
+        }
+}
+
+// [[a, i c], [i e, g]] with a, c, e, g real (rotations about X).
+template <int B, typename R, typename V, int P>
+__device__ __forceinline__ void rg_1x(const V (&s)[P], V (&d)[P], const R* m) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!(i & (1 << B))) {
+            const V a = s[i], b = s[i | (1 << B)];
+            V x, y;
+            x.x = fmaR(-m[3], b.y, m[0] * a.x);
+            x.y = fmaR(m[3], b.x, m[0] * a.y);
+            y.x = fmaR(-m[5], a.y, m[6] * b.x);
+            y.y = fmaR(m[5], a.x, m[6] * b.y);
+            d[i] = x;
+            d[i | (1 << B)] = y;
+        }
+}
+
 template <typename R, typename V>
 __device__ __forceinline__ V cmul(const V& a, R dr, R di) {
     V o;
@@ -139,11 +174,15 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
 // state 1 only (the host lowers a control-state-0 gate to a 2-qubit gate),
 // and 2-qubit gates with r0 < r1 (the host permutes the matrix), which keeps
 // the number of compiled cases -- and the instruction footprint -- small.
+// `each` hands the case body every (source, destination) register-array pair
+// it applies to: one state, or a state and its co-state in the same dispatch.
+#define QSV_EACH(...) each([&](const auto& s, auto& d) __attribute__((always_inline)) { __VA_ARGS__; })
 #define QSV_C1(KD, B)                                                          \
     case (KD) * 64 + (B) * 8:                                                  \
         if constexpr ((B) < RB) {                                              \
-            if constexpr ((KD) == DK_1Q) rg_1q<(B)>(s, d, g.m);                \
-            else rg_1d<(B)>(s, d, g.m);                                        \
+            if constexpr ((KD) == DK_1Q) QSV_EACH(rg_1q<(B)>(s, d, m));        \
+            else if constexpr ((KD) == DK_1R) QSV_EACH(rg_1r<(B)>(s, d, m));   \
+            else QSV_EACH(rg_1d<(B)>(s, d, m));                                \
         } else {                                                               \
             __builtin_unreachable();                                           \
         }                                                                      \
@@ -151,10 +190,10 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
 #define QSV_C2(KD, A, B)                                                       \
     case (KD) * 64 + (A) * 8 + (B):                                            \
         if constexpr ((A) < RB && (B) < RB && (A) != (B) && ((KD) != DK_2Q || (A) < (B))) { \
-            if constexpr ((KD) == DK_2Q) rg_2q<(A), (B)>(s, d, g.m);           \
-            else if constexpr ((KD) == DK_CX) rg_cx<(A), (B)>(s, d);           \
-            else if constexpr ((KD) == DK_CD) rg_cd<(A), (B)>(s, d, g.m);      \
-            else rg_c1q<(A), (B)>(s, d, g.m);                                  \
+            if constexpr ((KD) == DK_2Q) QSV_EACH(rg_2q<(A), (B)>(s, d, m));   \
+            else if constexpr ((KD) == DK_CX) QSV_EACH(rg_cx<(A), (B)>(s, d)); \
+            else if constexpr ((KD) == DK_CD) QSV_EACH(rg_cd<(A), (B)>(s, d, m)); \
+            else QSV_EACH(rg_c1q<(A), (B)>(s, d, m));                          \
         } else {                                                               \
             __builtin_unreachable();                                           \
         }                                                                      \
@@ -168,16 +207,21 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
 // Opcode of a gate: kind * 64 + r0 * 8 + r1; kOpCopy is d = s.
 constexpr int kOpCopy = 7 * 64;
 
-template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_op(const V (&s)[P], V (&d)[P], int op, const R* m) {
-    struct { const R* m; } g{m};
+template <typename V, int P>
+__device__ __forceinline__ void copy_regs(const V (&s)[P], V (&d)[P]) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) d[u] = s[u];
+}
+
+template <int RB, typename R, typename EACH>
+__device__ __forceinline__ void apply_op_each(int op, const R* m, EACH&& each) {
     switch (op) {
     case kOpCopy:
-#pragma unroll
-        for (int u = 0; u < P; ++u) d[u] = s[u];
+        QSV_EACH(copy_regs(s, d));
         break;
         QSV_C1ALL(DK_1Q)
         QSV_C1ALL(DK_1D)
+        QSV_C1ALL(DK_1R)
         QSV_C2ALL(DK_C1Q)
         QSV_C2ALL(DK_CX)
         QSV_C2ALL(DK_CD)
@@ -185,10 +229,27 @@ __device__ __forceinline__ void apply_op(const V (&s)[P], V (&d)[P], int op, con
     default: __builtin_unreachable();
     }
 }
+
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_op(const V (&s)[P], V (&d)[P], int op, const R* m) {
+    apply_op_each<RB>(op, m, [&](auto&& f) __attribute__((always_inline)) { f(s, d); });
+}
+
+// The same gate on two states (the adjoint sweep's state and co-state).
+template <int RB, typename R, typename V, int P>
+__device__ __forceinline__ void apply_op2(const V (&s1)[P], V (&d1)[P], const V (&s2)[P], V (&d2)[P],
+                                          int op, const R* m) {
+    apply_op_each<RB>(op, m, [&](auto&& f) __attribute__((always_inline)) {
+        f(s1, d1);
+        f(s2, d2);
+    });
+}
+
 template <int RB, typename R, typename V, int P>
 __device__ __forceinline__ void apply_gate(const V (&s)[P], V (&d)[P], const TGate<R>& g) {
     apply_op<RB>(s, d, g.kind * 64 + g.r0 * 8 + g.r1, g.m);
 }
+#undef QSV_EACH
 #undef QSV_C1ALL
 #undef QSV_C2ALL
 #undef QSV_C2ROW

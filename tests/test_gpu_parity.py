@@ -157,14 +157,17 @@ def test_fused_multi_tile_vs_oracle(q, ctx, n, seed):
     assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
 
 
-@pytest.mark.parametrize("tb,lb", [(10, 1), (10, 8), (11, 3), (12, 3), (12, 8), (12, 10)])
-def test_tile_shapes_agree(q, ctx, tb, lb):
+@pytest.mark.parametrize("lr", [1, 2])
+@pytest.mark.parametrize("tb,lb", [(10, 1), (10, 8), (11, 3), (12, 3), (12, 8), (12, 10), (13, 3)])
+def test_tile_shapes_agree(q, ctx, tb, lb, lr):
+    """Every tile size, low-bit count and both LDS exchanges (whole tile,
+    or two half-tile rounds) against the oracle."""
     n = 14
     c = W.random_mix(n, 80, seed=tb * 10 + lb)
     ref = O.run(c)
     c2 = q.Context()
-    c2.set_tile(q.QSV_C128, tb, lb)
-    c2.set_tile(q.QSV_C64, tb + 1, lb)
+    c2.set_tile(q.QSV_C128, tb, lb, 0, lr)
+    c2.set_tile(q.QSV_C64, min(tb + 1, 13), lb, 0, lr)
     st = make_state(q, c2, n)
     st.apply_circuit(c.gates)
     assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
@@ -200,15 +203,16 @@ def permutation_mix(n, ngates, seed):
     return W.Circuit(n, gates, name="permutation_mix")
 
 
-@pytest.mark.parametrize("tb,lb,rb", [(12, 3, 4), (11, 3, 3), (10, 3, 2), (12, 3, 3), (13, 3, 5)])
-def test_permutation_gates_at_stage_ends(q, tb, lb, rb):
+@pytest.mark.parametrize("lr", [1, 2])
+@pytest.mark.parametrize("tb,lb,rb", [(12, 3, 4), (11, 3, 3), (10, 3, 2), (12, 3, 3), (13, 3, 5), (13, 3, 4)])
+def test_permutation_gates_at_stage_ends(q, tb, lb, rb, lr):
     n = 14
     c = permutation_mix(n, 160, seed=tb * 100 + rb)
     phi = W.random_state(n, 77)
     ref = O.run(c, phi)
     c2 = q.Context()
-    c2.set_tile(q.QSV_C128, tb, lb, rb)
-    c2.set_tile(q.QSV_C64, tb, lb + 1 if lb < 4 else lb, rb)
+    c2.set_tile(q.QSV_C128, tb, lb, rb, lr)
+    c2.set_tile(q.QSV_C64, tb, lb + 1 if lb < 4 else lb, rb, lr)
     st = make_state(q, c2, n, init=phi)
     st.apply_circuit(c.gates)
     assert np.max(np.abs(st.to_numpy() - ref)) <= TOL128
@@ -217,6 +221,15 @@ def test_permutation_gates_at_stage_ends(q, tb, lb, rb):
     assert infidelity(s64.to_numpy(), ref) <= 1e-6
     st.free()
     s64.free()
+    c2.close()
+
+
+def test_set_tile_rejects_bad_shapes(q):
+    c2 = q.Context()
+    for args in [(14, 3, 0, 0), (9, 3, 0, 0), (12, 11, 0, 0), (12, 3, 6, 0), (13, 3, 3, 0), (12, 3, 4, 3)]:
+        with pytest.raises(q.QsvError):
+            c2.set_tile(q.QSV_C128, *args)
+    c2.set_tile(q.QSV_C128, 13, 3, 5, 2)    # the defaults, spelled out
     c2.close()
 
 

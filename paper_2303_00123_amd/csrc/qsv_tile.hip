@@ -48,9 +48,16 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
                                                               size_t(nst) * sizeof(TStage));
     const uint32_t tid = threadIdx.x;
 
+    // Tile of this workgroup.  Workgroups go to the 8 XCDs round-robin
+    // (block b on XCD b % 8); give each XCD a contiguous run of tiles in
+    // dispatch order, so tiles that differ only in the lowest non-tile bits
+    // (which share 128-byte lines when the tile keeps fewer than 3 or 4 low
+    // bits) are resident together on one XCD and meet in its L2.
+    const uint32_t ntiles = gridDim.x;
+    uint64_t b = blockIdx.x;
+    if ((ntiles & 7u) == 0) b = (blockIdx.x & 7u) * (ntiles >> 3) + (blockIdx.x >> 3);
     // per-thread pointer to this tile's slot-0 amplitude; slot u adds the
     // uniform offset du[u] (disjoint bits, so OR == ADD)
-    uint64_t b = blockIdx.x;
 #pragma unroll
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
     V* const sp = s + (b | deposit(tid, hdr->tpos_ld, TB));

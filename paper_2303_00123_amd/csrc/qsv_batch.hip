@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
                                                     double* __restrict__ partials,
                                                     double* __restrict__ out, unsigned spin_limit) {
     using V = typename V2T<R>::type;
-    constexpr int E = 1 << K;
+    constexpr bool SPLIT = K >= 13;   // as planned by build_batch
+    constexpr int E = SPLIT ? 1 << (K - 1) : 1 << K;
     constexpr int RB = K - 8;
     constexpr int P = 1 << RB;
     __shared__ V tile[E];
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
                 for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
             }
         }
-        if (ok) run_stages<R, K, K - 8>(v, lds, stg, nst, gates, tid);
+        if (ok) run_stages<R, K, K - 8, SPLIT>(v, lds, stg, nst, gates, tid);
 
         if (Pp.flags & BP_LAST) {
             double acc = 0.0;
@@ -241,45 +242,13 @@ void parallel_for(int n, F&& f) {
 }
 
 // A pass of one gate (or none) would run as an unfused kernel in the
-// single-state path; here every pass is a tile pass, so give it one register
-// stage holding the gate (between canonical load and store stages when the
-// gate touches a low local bit).
-void make_single_stage(Pass& ps, const std::vector<PGate>& gates, int K) {
+// single-state path; here every pass is a tile pass, so it gets register
+// stages like any other.
+void make_single_stage(Pass& ps, const std::vector<PGate>& gates, int K, bool split) {
     ps.single = false;
-    ps.stages.clear();
     ps.rb = K - 8;
-    Stage st;
-    st.nr = K - 8;
-    for (int j = 0; j < st.nr; ++j) st.rbits[j] = 8 + j;
-    uint64_t need = 0;
-    int loc[64];
-    for (int q = 0; q < 64; ++q) loc[q] = -1;
-    for (int b = 0; b < ps.k; ++b) loc[ps.pos[b]] = b;
-    for (int gi : ps.gates) {
-        const PGate& x = gates[size_t(gi)];
-        need |= uint64_t(1) << loc[x.p0];
-        if (!is_1q(x.kind)) need |= uint64_t(1) << loc[x.p1];
-    }
-    st.gates = ps.gates;
-    if (need & 0xFF) {   // a low local bit: use a register set holding the gate's bits
-        int j = 0;
-        for (int b = 0; b < ps.k && j < st.nr; ++b)
-            if ((need >> b) & 1) st.rbits[j++] = b;
-        for (int b = ps.k - 1; b >= 0 && j < st.nr; --b)
-            if (!((need >> b) & 1)) {
-                need |= uint64_t(1) << b;
-                st.rbits[j++] = b;
-            }
-        std::sort(st.rbits, st.rbits + st.nr);
-        Stage s0, s2;   // canonical load stage and store stage around it
-        s0.nr = s2.nr = st.nr;
-        for (int j2 = 0; j2 < st.nr; ++j2) s0.rbits[j2] = s2.rbits[j2] = 8 + j2;
-        ps.stages.push_back(s0);
-        ps.stages.push_back(st);
-        ps.stages.push_back(s2);
-    } else {
-        ps.stages.push_back(st);
-    }
+    ps.split = split;
+    plan_pass_stages(ps.k, gates, ps);
 }
 
 // Plan every circuit and lay out the device tables.  Returns an error text
@@ -300,7 +269,9 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
     // per circuit, in parallel: lower, fuse, plan (structure hash per circuit)
     std::vector<std::string> errs(static_cast<size_t>(nb));
     std::vector<uint64_t> chash(static_cast<size_t>(nb), 1469598103934665603ull);
-    const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype)};
+    // 2^13-amplitude tiles (32 per thread) need the split exchange to fit
+    // two workgroups per compute unit
+    const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype), K >= 13 ? 1 : 0};
     parallel_for(nb, [&](int c) {
         const int n = nq[c];
         const int ne = n < K ? K : n;
@@ -349,13 +320,14 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             Pass ps;
             ps.k = K;
             ps.rb = K - 8;
+            ps.coal = bcfg.coal_bits;
             for (int b = 0; b < K; ++b) ps.pos[b] = b;
             pl.push_back(ps);
         }
         // a pass of one gate would run as an unfused kernel in the
         // single-state path; here every pass is a tile pass
         for (Pass& ps : pl)
-            if (ps.single || ps.stages.empty()) make_single_stage(ps, pg, K);
+            if (ps.single || ps.stages.empty()) make_single_stage(ps, pg, K, bcfg.split != 0);
     });
     for (int c = 0; c < nb; ++c)
         if (!errs[size_t(c)].empty()) return errs[size_t(c)];
@@ -496,6 +468,12 @@ hipError_t launch_batch_k(qsv_ctx ctx, hipStream_t stream, int K, const char* de
     case 10: return launch_batch<R, 10>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
     case 11: return launch_batch<R, 11>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
     case 12: return launch_batch<R, 12>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
+    case 13:
+        // complex128 at 2^13: two 32-amplitude register sets leave no room
+        // for the batch bookkeeping within 256 registers
+        if constexpr (sizeof(R) == 4)
+            return launch_batch<R, 13>(ctx, stream, dev, L, nb, nitems, states, ctr, partials, out);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -658,7 +636,7 @@ static uint64_t shape_key(int nb, const int* nq, const int64_t* gate_off, const 
 }
 
 // Tile shapes the autotuner tries for a batch, best first by default.
-static const int kTuneShapes[][2] = {{12, 3}, {11, 3}, {10, 2}, {12, 4}, {11, 2}, {10, 3}};
+static const int kTuneShapes[][2] = {{13, 3}, {12, 3}, {11, 3}, {10, 2}, {13, 4}, {12, 4}, {11, 2}, {10, 3}};
 
 }  // namespace qsv
 
@@ -705,7 +683,7 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
     // tile shape: the tuned choice for this batch shape, if any
     BatchRun R;
     uint64_t key = 0;
-    int K = 12, L = dtype == QSV_C128 ? 3 : 4;
+    int K = dtype == QSV_C128 ? 12 : 13, L = dtype == QSV_C128 ? 3 : 4;
     {
         key = shape_key(nb, nq, gate_off, g, term_off, qmasks, dtype);
         qsv_status s = QSV_OK;
@@ -717,6 +695,7 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
             // time each candidate once (every run computes the full, correct batch)
             double best = 1e30;
             for (const auto& sh : kTuneShapes) {
+                if (sh[0] >= 13 && dtype == QSV_C128) continue;   // not compiled (see launch_batch_k)
                 uint64_t k2 = 0;
                 BatchRun Rc;
                 s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,

@@ -78,6 +78,8 @@ bool tile_shape_supported(int dtype, int tile_bits, int reg_bits);
 // Group gates into passes (greedy, dependency-respecting), then split each
 // tile pass into register stages.
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg);
+// Register stages of one pass whose k, rb, coal, split, pos and gates are set.
+void plan_pass_stages(int n, const std::vector<PGate>& gates, Pass& ps);
 
 // Fuse the gates of one register stage (indices into `gates`, in execution
 // order): 1-qubit gates are multiplied into the next 2-qubit or controlled

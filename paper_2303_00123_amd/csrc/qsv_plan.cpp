@@ -443,6 +443,8 @@ std::vector<PGate> prefuse(const std::vector<PGate>& gates) {
     return fuse_stage(gates, all);
 }
 
+void plan_pass_stages(int n, const std::vector<PGate>& gates, Pass& ps) { plan_stages(n, gates, ps); }
+
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {
     std::vector<Pass> passes;
     std::vector<uint64_t> masks(gates.size());

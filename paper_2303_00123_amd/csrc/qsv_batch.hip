@@ -94,7 +94,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
     for (;;) {
         if (tid == 0) s_item = int(atomicAdd(&ctr[0], 1u));
         __syncthreads();
-        const int it = s_item;
+        // the same for every lane: scalar loads and registers for the item's tables
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= nitems) return;   // uniform: every wave of the workgroup leaves
         const BItem I = items[it];
         const BPass Pp = passes[I.pass];
@@ -109,9 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
 #pragma unroll
         for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
         const uint64_t xt = b | deposit(tid, hdr->tpos_ld, 8);   // register slot 0 (load mapping)
-        const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);   // register slot 0 (store mapping)
         V* const sp = states + C.state_off + xt;
-        V* const sq = states + C.state_off + xs;
 
         V v[P];
         bool ok = true;
@@ -148,6 +147,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
             }
         }
         if (ok) run_stages<R, K, K - 8, SPLIT>(v, lds, stg, nst, gates, tid);
+        // store mapping, computed after the stages so it is not live across them
+        const uint64_t xs = b | deposit(tid, hdr->tpos_st, 8);   // register slot 0
+        V* const sq = states + C.state_off + xs;
 
         if (Pp.flags & BP_LAST) {
             double acc = 0.0;

@@ -48,6 +48,9 @@ def test_fused_adjoint_vs_unfused_and_oracle(q, ctx, maker):
     assert np.max(np.abs(g2 - g_ref)) <= tol
     sel = list(range(0, len(c.params), 7))
     assert np.max(np.abs(g1[sel] - O.param_shift(c, sel))) <= tol
+    # the oracle's central finite differences (h = 1e-6): truncation ~h^2,
+    # rounding ~1e-16 |f| / h
+    assert np.max(np.abs(g1[sel[:5]] - O.finite_diff(c, sel[:5]))) <= 1e-7 * wsum(c)
     # psi is rewound to |0...0>
     v = psi.to_numpy()
     assert abs(v[0] - 1.0) <= 1e-10 and abs(np.linalg.norm(v) - 1.0) <= 1e-10
@@ -83,6 +86,15 @@ def test_config5_adjoint_vs_gpu_parameter_shift(q, ctx):
         fm = energy(p)
         assert abs(g[j] - 0.5 * (fp - fm)) <= 1e-10 * wsum(c), j
     assert np.max(np.abs(g - g_unf)) <= 1e-11 * wsum(c)
+    # central finite differences, h = 1e-6, FP64 forward passes
+    h = 1e-6
+    for j in sel[:8]:
+        p = c.params.copy()
+        p[j] += h
+        fp = energy(p)
+        p[j] -= 2 * h
+        fm = energy(p)
+        assert abs(g[j] - (fp - fm) / (2 * h)) <= 1e-6 * wsum(c), j
     p64, l64 = q.State(ctx, c.n, q.QSV_C64), q.State(ctx, c.n, q.QSV_C64)
     g64 = q.adjoint(p64, l64, c.gates, c.params, c.observable)[1]
     assert np.max(np.abs(g64 - g)) <= 1e-4 * wsum(c)

@@ -96,3 +96,51 @@ def test_c64_matches_c128_full_size(q, ctx):
     assert abs(b.norm2() - 1.0) <= 1e-5
     b.free()
     a.free()
+
+
+def test_config2_28_qubits_fused_vs_one_kernel_per_gate(q, ctx):
+    """28-qubit brick circuit (20 layers): the fused tile passes the benchmark
+    times against one kernel per gate (Algs. 1-3, separately checked against
+    the oracle), amplitude by amplitude on the GPU; norm and <Z0 Z27>."""
+    import torch
+    c = W.config2()
+    a = q.State(ctx, c.n)
+    a.init_basis(0)
+    a.apply_circuit(c.gates)
+    b = q.State(ctx, c.n)
+    b.init_basis(0)
+    b.apply_circuit(c.gates, flags=q.FLAG_NO_FUSE)
+    assert torch.max(torch.abs(a.tensor - b.tensor)).item() <= 1e-12
+    assert abs(a.norm2() - 1.0) <= 1e-11
+    za, _ = a.expect_z([((0, c.n - 1), 1.0)])
+    zb, _ = b.expect_z([((0, c.n - 1), 1.0)])
+    assert abs(za[0] - zb[0]) <= 1e-12 and abs(za[0]) <= 1.0
+    a.free()
+    b.free()
+
+
+def test_config3_32_qubits_c64_vs_c128(q):
+    """32-qubit Haar-pairs circuit (10 layers) in complex128 (64 GiB) and
+    complex64 (32 GiB): infidelity of the complex64 state, norm, and the
+    circuit followed by its inverse; the same structure at 28 qubits too."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100 * 2 ** 30:
+        pytest.skip("needs ~100 GiB of device memory")
+    ctx = q.Context()
+    for n in (28, 32):
+        c = W.layered_haar_pairs(n, 10, 1003)
+        a = q.State(ctx, n, q.QSV_C128)
+        a.init_basis(0)
+        a.apply_circuit(c.gates)
+        b = q.State(ctx, n, q.QSV_C64)
+        b.init_basis(0)
+        b.apply_circuit(c.gates)
+        assert abs(a.norm2() - 1.0) <= 1e-10
+        assert 1.0 - abs(b.inner(a)) ** 2 <= 1e-6, n
+        b.free()
+        if n == 32:
+            a.apply_circuit(W.inverse(c).gates)
+            assert abs(complex(a.tensor[0].item()) - 1.0) <= 1e-10
+        a.free()
+    ctx.close()

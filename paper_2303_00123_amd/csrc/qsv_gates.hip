@@ -18,6 +18,40 @@ struct PPT<double> { static constexpr int value = 4; };
 template <>
 struct PPT<float> { static constexpr int value = 8; };
 
+// Gate kernels: pairs (quads) per thread.  Few per thread and many
+// workgroups, with non-temporal loads and stores (the state streams through
+// once per gate, so it should not displace other lines from the caches),
+// measured best on MI355X: 67-77 % of the HBM peak at 30 qubits against
+// 65-67 % with 4 pairs per thread and ordinary accesses.
+template <typename R>
+struct GatePairs;
+template <>
+struct GatePairs<double> { static constexpr int value = 1; };
+template <>
+struct GatePairs<float> { static constexpr int value = 2; };
+template <typename R>
+struct GateQuads { static constexpr int value = 1; };
+
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) {
+    using R = decltype(p->x);
+    typedef R VX __attribute__((ext_vector_type(2)));
+    const VX x = __builtin_nontemporal_load(reinterpret_cast<const VX*>(p));
+    V v;
+    v.x = x.x;
+    v.y = x.y;
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ void st_nt(V* p, const V& v) {
+    using R = decltype(p->x);
+    typedef R VX __attribute__((ext_vector_type(2)));
+    VX x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<VX*>(p));
+}
+
 // ---------------------------------------------------------------- |b>
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* __restrict__ s,
@@ -43,7 +77,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __restrict__ s,
                                                       uint64_t npairs, int p, M2<R> u) {
     using V = typename V2T<R>::type;
-    constexpr int P = PPT<R>::value;
+    constexpr int P = GatePairs<R>::value;
     const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
     const uint64_t w = uint64_t(1) << p;
     V a[P], b[P];
@@ -52,8 +86,8 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
         const uint64_t j = j0 + uint64_t(k) * kThreads;
         if (j < npairs) {
             const uint64_t ia = insert0(j, p);
-            a[k] = s[ia];
-            b[k] = s[ia + w];
+            a[k] = ld_nt(s + ia);
+            b[k] = ld_nt(s + ia + w);
         }
     }
 #pragma unroll
@@ -63,8 +97,8 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
             const uint64_t ia = insert0(j, p);
             V oa, ob;
             mv2(u.v, a[k], b[k], oa, ob);
-            s[ia] = oa;
-            s[ia + w] = ob;
+            st_nt(s + ia, oa);
+            st_nt(s + ia + w, ob);
         }
     }
 }
@@ -77,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
                                                        uint64_t npairs, int plo, int phi, int pc,
                                                        int pt, int cs, M2<R> u) {
     using V = typename V2T<R>::type;
-    constexpr int P = PPT<R>::value;
+    constexpr int P = GatePairs<R>::value;
     const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
     const uint64_t wt = uint64_t(1) << pt;
     const uint64_t wc = cs ? (uint64_t(1) << pc) : 0;
@@ -87,8 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
         const uint64_t j = j0 + uint64_t(k) * kThreads;
         if (j < npairs) {
             const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
-            a[k] = s[ia];
-            b[k] = s[ia + wt];
+            a[k] = ld_nt(s + ia);
+            b[k] = ld_nt(s + ia + wt);
         }
     }
 #pragma unroll
@@ -98,8 +132,8 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
             const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
             V oa, ob;
             mv2(u.v, a[k], b[k], oa, ob);
-            s[ia] = oa;
-            s[ia + wt] = ob;
+            st_nt(s + ia, oa);
+            st_nt(s + ia + wt, ob);
         }
     }
 }
@@ -112,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
                                                       uint64_t nquads, int plo, int phi, int pa,
                                                       int pb, M4<R> u) {
     using V = typename V2T<R>::type;
-    constexpr int P = PPT<R>::value / 2;
+    constexpr int P = GateQuads<R>::value;
     const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
     const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
     V v[P][4];
@@ -121,10 +155,10 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
         const uint64_t j = j0 + uint64_t(k) * kThreads;
         if (j < nquads) {
             const uint64_t i0 = insert0(insert0(j, plo), phi);
-            v[k][0] = s[i0];
-            v[k][1] = s[i0 + wb];
-            v[k][2] = s[i0 + wa];
-            v[k][3] = s[i0 + wa + wb];
+            v[k][0] = ld_nt(s + i0);
+            v[k][1] = ld_nt(s + i0 + wb);
+            v[k][2] = ld_nt(s + i0 + wa);
+            v[k][3] = ld_nt(s + i0 + wa + wb);
         }
     }
 #pragma unroll
@@ -134,10 +168,10 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
             const uint64_t i0 = insert0(insert0(j, plo), phi);
             V o[4];
             mv4(u.v, v[k], o);
-            s[i0] = o[0];
-            s[i0 + wb] = o[1];
-            s[i0 + wa] = o[2];
-            s[i0 + wa + wb] = o[3];
+            st_nt(s + i0, o[0]);
+            st_nt(s + i0 + wb, o[1]);
+            st_nt(s + i0 + wa, o[2]);
+            st_nt(s + i0 + wa + wb, o[3]);
         }
     }
 }
@@ -178,7 +212,7 @@ hipError_t apply1q_t(qsv_ctx ctx, void* s, int n, int p, const double* u) {
     const uint64_t np = uint64_t(1) << (n - 1);
     prof_before(ctx, sizeof(R) == 8 ? "apply1q_c128" : "apply1q_c64",
                 2.0 * double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL(k_apply1q<R>, dim3(grid_for<R>(np, PPT<R>::value)), dim3(kThreads), 0,
+    hipLaunchKernelGGL(k_apply1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
                        ctx->stream, static_cast<V*>(s), np, p, to_m2<R>(u));
     prof_after(ctx);
     return hipGetLastError();
@@ -191,7 +225,7 @@ hipError_t applyc1q_t(qsv_ctx ctx, void* s, int n, int pc, int pt, int cs, const
     const int plo = pc < pt ? pc : pt, phi = pc < pt ? pt : pc;
     prof_before(ctx, sizeof(R) == 8 ? "applyc1q_c128" : "applyc1q_c64",
                 double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL(k_applyc1q<R>, dim3(grid_for<R>(np, PPT<R>::value)), dim3(kThreads), 0,
+    hipLaunchKernelGGL(k_applyc1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
                        ctx->stream, static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
     prof_after(ctx);
     return hipGetLastError();
@@ -204,7 +238,7 @@ hipError_t apply2q_t(qsv_ctx ctx, void* s, int n, int pa, int pb, const double* 
     const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
     prof_before(ctx, sizeof(R) == 8 ? "apply2q_c128" : "apply2q_c64",
                 2.0 * double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL(k_apply2q<R>, dim3(grid_for<R>(nq, PPT<R>::value / 2)), dim3(kThreads), 0,
+    hipLaunchKernelGGL(k_apply2q<R>, dim3(grid_for<R>(nq, GateQuads<R>::value)), dim3(kThreads), 0,
                        ctx->stream, static_cast<V*>(s), nq, plo, phi, pa, pb, to_m4<R>(u));
     prof_after(ctx);
     return hipGetLastError();

@@ -201,8 +201,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     V v[P], l[P];
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-        v[u] = sp[hdr->du[u]];
-        l[u] = sl[hdr->du[u]];
+        v[u] = ld_nt(sp + hdr->du[u]);
+        l[u] = ld_nt(sl + hdr->du[u]);
     }
     for (int st = 0; st < nst; ++st) {
         const TStage& S = stg[st];
@@ -266,8 +266,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     V* const sm = lam + xs;
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-        sq[hdr->du_st[u]] = v[u];
-        sm[hdr->du_st[u]] = l[u];
+        st_nt(sq + hdr->du_st[u], v[u]);
+        st_nt(sm + hdr->du_st[u], l[u]);
     }
 }
 

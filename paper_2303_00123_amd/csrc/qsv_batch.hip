@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (ok) {
 #pragma unroll
-                for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
+                for (int u = 0; u < P; ++u) v[u] = ld_nt(sp + hdr->du[u]);
             }
         }
         if (ok) run_stages<R, K, K - 8, SPLIT>(v, lds, stg, nst, gates, tid);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(typename V2T<R>::type* __res
         } else {
             if (ok) {
 #pragma unroll
-                for (int u = 0; u < P; ++u) sq[hdr->du_st[u]] = v[u];
+                for (int u = 0; u < P; ++u) st_nt(sq + hdr->du_st[u], v[u]);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();

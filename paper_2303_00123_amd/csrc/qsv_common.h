@@ -31,6 +31,28 @@ __device__ __forceinline__ uint32_t insert0_32(uint32_t j, int p) {
     return ((j ^ lo) << 1) | lo;
 }
 
+// Non-temporal load and store of one amplitude: passes stream the state
+// through once, so its lines should not displace other cached data.
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) {
+    using R = decltype(p->x);
+    typedef R VX __attribute__((ext_vector_type(2)));
+    const VX x = __builtin_nontemporal_load(reinterpret_cast<const VX*>(p));
+    V v;
+    v.x = x.x;
+    v.y = x.y;
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ void st_nt(V* p, const V& v) {
+    using R = decltype(p->x);
+    typedef R VX __attribute__((ext_vector_type(2)));
+    VX x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<VX*>(p));
+}
+
 // Fused multiply-add in the state's real type.
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

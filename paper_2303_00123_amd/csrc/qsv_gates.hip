@@ -32,26 +32,6 @@ struct GatePairs<float> { static constexpr int value = 2; };
 template <typename R>
 struct GateQuads { static constexpr int value = 1; };
 
-template <typename V>
-__device__ __forceinline__ V ld_nt(const V* p) {
-    using R = decltype(p->x);
-    typedef R VX __attribute__((ext_vector_type(2)));
-    const VX x = __builtin_nontemporal_load(reinterpret_cast<const VX*>(p));
-    V v;
-    v.x = x.x;
-    v.y = x.y;
-    return v;
-}
-template <typename V>
-__device__ __forceinline__ void st_nt(V* p, const V& v) {
-    using R = decltype(p->x);
-    typedef R VX __attribute__((ext_vector_type(2)));
-    VX x;
-    x.x = v.x;
-    x.y = v.y;
-    __builtin_nontemporal_store(x, reinterpret_cast<VX*>(p));
-}
-
 // ---------------------------------------------------------------- |b>
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* __restrict__ s,

@@ -64,11 +64,11 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
 
     V v[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) v[u] = sp[hdr->du[u]];
+    for (int u = 0; u < P; ++u) v[u] = ld_nt(sp + hdr->du[u]);
     run_stages<R, K, RB, SPLIT>(v, lds, stg, nst, gates, tid);
     V* const sq = s + (b | deposit(tid, hdr->tpos_st, TB));
 #pragma unroll
-    for (int u = 0; u < P; ++u) sq[hdr->du_st[u]] = v[u];
+    for (int u = 0; u < P; ++u) st_nt(sq + hdr->du_st[u], v[u]);
 }
 
 // ------------------------------------------------------------ host side

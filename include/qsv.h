@@ -58,7 +58,8 @@ enum {
     QSV_ERR_HIP = 4,     /* a HIP runtime call failed (text in qsv_last_error)     */
     QSV_ERR_DTYPE = 5,   /* unknown dtype or mismatched dtypes                     */
     QSV_ERR_ALIGN = 6,   /* device pointer not 16-byte aligned                     */
-    QSV_ERR_SIZE = 7     /* buffer smaller than 2^n amplitudes / n out of range    */
+    QSV_ERR_SIZE = 7,    /* buffer smaller than 2^n amplitudes / n out of range    */
+    QSV_ERR_INTERNAL = 8 /* the planner produced an inconsistent plan (a bug)      */
 };
 
 enum { QSV_C64 = 1, QSV_C128 = 2 };
@@ -272,14 +273,16 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int
 /* Host-only query of the exact gate sequence the tile kernels would apply for
  * qsv_apply_circuit (no device work; needs no GPU): gates grouped into passes
  * and register stages, with the 1-qubit gates of a stage multiplied into the
- * neighbouring 2-qubit gates.  out receives up to `cap` records in execution
- * order (kind QSV_G1Q, QSV_GC1Q or QSV_G2Q with explicit matrices; rotations
- * are evaluated with params), pass_of_out[i] the pass of record i (either
- * output may be NULL); *nout receives the number of records, or the number
- * needed if cap is too small (then QSV_ERR_SIZE). */
+ * neighbouring 2-qubit gates.  Tile shape arguments as in qsv_set_tile.  The
+ * device records of every pass are built too (and discarded), so a planner
+ * inconsistency surfaces here as QSV_ERR_INTERNAL.  out receives up to `cap`
+ * records in execution order (kind QSV_G1Q, QSV_GC1Q or QSV_G2Q with explicit
+ * matrices; rotations are evaluated with params), pass_of_out[i] the pass of
+ * record i (either output may be NULL); *nout receives the number of
+ * records, or the number needed if cap is too small (then QSV_ERR_SIZE). */
 qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
-                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, qsv_gate* out,
-                          int64_t cap, int32_t* pass_of_out, int64_t* nout);
+                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, int lds_rounds,
+                          qsv_gate* out, int64_t cap, int32_t* pass_of_out, int64_t* nout);
 
 /* Host-only query of the fusion plan qsv_apply_circuit would use for an
  * n-qubit circuit (no device work; needs no GPU).  tile_bits / low_bits as in

@@ -223,24 +223,38 @@ void mix(uint64_t& h, uint64_t v) {
 }
 
 // f(0 .. n-1) on up to 16 host threads (work handed out one index at a
-// time); serial for small n.  f must not throw.
+// time); serial for small n.  False if f threw (out of host memory): the
+// exception stops at the worker instead of ending the process.
 template <typename F>
-void parallel_for(int n, F&& f) {
+bool parallel_for(int n, F&& f) {
+    std::atomic<bool> ok{true};
+    auto guarded = [&](int i) {
+        try {
+            f(i);
+        } catch (...) {
+            ok = false;
+        }
+    };
     const unsigned hw = std::thread::hardware_concurrency();
     const int nt = std::min(std::min(int(hw ? hw : 1), 16), n);
     if (nt <= 1 || n < 8) {
-        for (int i = 0; i < n; ++i) f(i);
-        return;
+        for (int i = 0; i < n; ++i) guarded(i);
+        return ok;
     }
     std::atomic<int> next{0};
     auto work = [&]() {
-        for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+        for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) guarded(i);
     };
     std::vector<std::thread> th;
     th.reserve(size_t(nt - 1));
-    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    try {
+        for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    } catch (...) {
+        // fewer threads than asked for: the ones started (and this one) finish the work
+    }
     work();
     for (std::thread& x : th) x.join();
+    return ok;
 }
 
 // A pass of one gate (or none) would run as an unfused kernel in the
@@ -274,7 +288,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
     // 2^13-amplitude tiles (32 per thread) need the split exchange to fit
     // two workgroups per compute unit
     const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype), K >= 13 ? 1 : 0};
-    parallel_for(nb, [&](int c) {
+    const bool built = parallel_for(nb, [&](int c) {
         const int n = nq[c];
         const int ne = n < K ? K : n;
         const int64_t g0 = gate_off[c], g1 = gate_off[c + 1];
@@ -331,6 +345,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
         for (Pass& ps : pl)
             if (ps.single || ps.stages.empty()) make_single_stage(ps, pg, K, bcfg.split != 0);
     });
+    if (!built) return "out of host memory while planning";
     for (int c = 0; c < nb; ++c)
         if (!errs[size_t(c)].empty()) return errs[size_t(c)];
     for (int c = 0; c < nb; ++c) mix(B.shape_key, chash[size_t(c)]);
@@ -383,13 +398,14 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
         B.plan.assign(total, 0);
     }
     std::atomic<bool> bad{false};
-    parallel_for(nb, [&](int c) {
+    const bool written = parallel_for(nb, [&](int c) {
         const std::vector<Pass>& pl = *plans[size_t(c)];
         for (size_t p = 0; p < pl.size(); ++p) {
             const size_t off = B.passes[rec_first[size_t(c)] + p].rec_off;
             if (!write_pass_record(dtype, B.plan.data() + off, lowered[size_t(c)], pl[p])) bad = true;
         }
     });
+    if (!written) return "out of host memory while writing records";
     if (bad) return "internal planner error";
     if (B.plan.size() >= (size_t(1) << 32)) return "batch plan too large";
     // items, pass-level-major; within a level, larger circuits first

@@ -231,6 +231,7 @@ const char* qsv_status_str(qsv_status s) {
     case QSV_ERR_DTYPE: return "invalid or mismatched dtype";
     case QSV_ERR_ALIGN: return "misaligned device pointer";
     case QSV_ERR_SIZE: return "invalid size";
+    case QSV_ERR_INTERNAL: return "internal planner error";
     default: return "unknown status";
     }
 }
@@ -735,18 +736,26 @@ qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int
 }
 
 qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
-                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, qsv_gate* out,
-                          int64_t cap, int32_t* pass_of_out, int64_t* nout) {
+                          int64_t nparams, int tile_bits, int low_bits, int reg_bits, int lds_rounds,
+                          qsv_gate* out, int64_t cap, int32_t* pass_of_out, int64_t* nout) {
     if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
     if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
     if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
     std::string err;
     TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, 0, cfg, err)) return s;
+    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err)) return s;
     std::vector<PGate> pg;
     if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
     if (n >= kMinTileBits) pg = prefuse(pg);
     std::vector<Pass> passes = plan_passes(n, pg, cfg);
+    {
+        std::vector<char> rec;
+        for (const Pass& ps : passes) {
+            if (ps.single || ps.stages.empty()) continue;
+            rec.assign(pass_record_bytes(dtype, ps), 0);
+            if (!write_pass_record(dtype, rec.data(), pg, ps)) return QSV_ERR_INTERNAL;
+        }
+    }
     int64_t k = 0;
     auto emit = [&](const PGate& x, int32_t p) {
         if (k < cap) {

@@ -24,7 +24,8 @@ AXES = {"X": 0, "Y": 1, "Z": 2}
 KINDS = {"1q": G1Q, "c1q": GC1Q, "2q": G2Q, "rot": GROT}
 
 STATUS = {0: "QSV_OK", 1: "QSV_ERR_ARG", 2: "QSV_ERR_QUBIT", 3: "QSV_ERR_NOMEM",
-          4: "QSV_ERR_HIP", 5: "QSV_ERR_DTYPE", 6: "QSV_ERR_ALIGN", 7: "QSV_ERR_SIZE"}
+          4: "QSV_ERR_HIP", 5: "QSV_ERR_DTYPE", 6: "QSV_ERR_ALIGN", 7: "QSV_ERR_SIZE",
+          8: "QSV_ERR_INTERNAL"}
 
 # C layout of qsv_gate: 6 x int32, then double[32] (offset 24), 280 bytes.
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("ctrl_state", "<i4"),
@@ -96,7 +97,7 @@ def lib():
         "qsv_profile_end": [vp, vp, i32, P(i32)],
         "qsv_set_tile": [vp, i32, i32, i32, i32, i32],
         "qsv_plan_circuit": [i32, i32, vp, i64, i32, i32, i32, P(i64), vp, vp, vp],
-        "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, i32, vp, i64, vp, P(i64)],
+        "qsv_plan_fused": [i32, i32, vp, i64, vp, i64, i32, i32, i32, i32, vp, i64, vp, P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -363,7 +364,7 @@ def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_b
 
 
 def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int = 0,
-               low_bits: int = 0, reg_bits: int = 0):
+               low_bits: int = 0, reg_bits: int = 0, lds_rounds: int = 0):
     """Host-only: the exact gate records the kernels apply, in order, and the
     pass index of each (see qsv_plan_fused)."""
     g = marshal_gates(gates)
@@ -373,7 +374,7 @@ def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int
     pas = np.zeros(cap, dtype=np.int32)
     nout = ctypes.c_int64()
     st = lib().qsv_plan_fused(n, dtype, _ptr(g), len(g), _ptr(p), p.size, tile_bits, low_bits,
-                              reg_bits, _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
+                              reg_bits, lds_rounds, _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_fused failed")
     return out[: nout.value], pas[: nout.value]

@@ -181,3 +181,42 @@ def test_fusion_reduces_dispatches_on_brick_circuit():
     c = W.layered_cnot_brick(30, 20, seed=3002)
     recs, pas = q.plan_fused(c.n, c.gates)
     assert len(recs) < 0.7 * len(c.gates)
+
+
+def _permutation_mix(n, ngates, seed):
+    rng = np.random.default_rng(seed)
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    SWAP = np.eye(4)[[0, 2, 1, 3]].astype(complex)
+    gates = []
+    for _ in range(ngates):
+        r = rng.random()
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        if r < 0.2:
+            gates.append(W.g1(a, X))
+        elif r < 0.45:
+            gates.append(W.gc(a, b, X, cs=int(rng.integers(2))))
+        elif r < 0.6:
+            gates.append(W.g2(a, b, SWAP))
+        elif r < 0.8:
+            gates.append(W.g1(a, W.haar_unitary(2, rng)))
+        else:
+            gates.append(W.g2(a, b, W.haar_unitary(4, rng)))
+    return W.Circuit(n, gates)
+
+
+@pytest.mark.parametrize("lr", [1, 2])
+@pytest.mark.parametrize("tb,lb,rb", [(10, 3, 2), (11, 3, 3), (12, 3, 3), (12, 3, 4), (12, 1, 4),
+                                      (13, 3, 4), (13, 3, 5), (13, 4, 5), (13, 0, 5)])
+def test_device_records_build_for_every_shape(tb, lb, rb, lr):
+    """Every pass of random, permutation-heavy and structured circuits yields
+    consistent device records (stage mappings, split-exchange shared bits,
+    folded permutation gates) for every compiled shape and both LDS
+    exchanges; the fused sequence still equals the circuit."""
+    for k, c in enumerate([W.random_mix(16, 150, seed=tb * 7 + rb), _permutation_mix(15, 200, seed=tb + lb),
+                           W.layered_cnot_brick(17, 6, seed=5), W.qft(14), W.hea_cz_ring(14, 3, seed=9)]):
+        for dtype in (q.QSV_C128, q.QSV_C64):
+            recs, pas = q.plan_fused(c.n, c.gates, c.params, dtype, tb, lb, rb, lr)
+            if k == 1 and dtype == q.QSV_C128:
+                phi = W.random_state(c.n, 3)
+                got = O.run(_records_to_circuit(c.n, recs), phi)
+                assert np.max(np.abs(got - O.run(c, phi))) < 1e-12

@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <map>
 #include <string>
 #include <thread>
@@ -664,144 +665,150 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                                     const qsv_gate* g, const double* params, int64_t nparams,
                                     const int64_t* term_off, const uint64_t* qmasks,
                                     const double* w, int dtype, double* out, int flags) {
-    if (!ctx) return QSV_ERR_ARG;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
-        ctx->last_error = "the context's device is not the current HIP device";
-        return QSV_ERR_ARG;
-    }
-    if (dtype != QSV_C64 && dtype != QSV_C128) {
-        ctx->last_error = "qsv_batch_run: dtype must be QSV_C64 or QSV_C128";
-        return QSV_ERR_DTYPE;
-    }
-    if (nb < 1 || !nq || !gate_off || !term_off || !out || (nparams > 0 && !params) || nparams < 0) {
-        ctx->last_error = "qsv_batch_run: bad arguments";
-        return QSV_ERR_ARG;
-    }
-    if (flags & ~(QSV_FLAG_CAPTURE_GRAPH | QSV_FLAG_TUNE)) {
-        ctx->last_error = "qsv_batch_run: unknown flag";
-        return QSV_ERR_ARG;
-    }
-    for (int c = 0; c < nb; ++c) {
-        if (nq[c] < 1 || nq[c] > kMaxBatchQubits) {
-            ctx->last_error = "qsv_batch_run: circuit " + std::to_string(c) + " has " +
-                              std::to_string(nq[c]) + " qubits (allowed 1.." +
-                              std::to_string(kMaxBatchQubits) + ")";
-            return QSV_ERR_SIZE;
-        }
-        if (gate_off[c + 1] < gate_off[c] || term_off[c + 1] < term_off[c]) {
-            ctx->last_error = "qsv_batch_run: offsets must be non-decreasing";
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+            ctx->last_error = "the context's device is not the current HIP device";
             return QSV_ERR_ARG;
         }
-    }
-    if (gate_off[0] != 0 || term_off[0] != 0 || (gate_off[nb] > 0 && !g) || (term_off[nb] > 0 && !qmasks)) {
-        ctx->last_error = "qsv_batch_run: bad offsets or arrays";
-        return QSV_ERR_ARG;
-    }
-    // tile shape: the tuned choice for this batch shape, if any
-    BatchRun R;
-    uint64_t key = 0;
-    int K = dtype == QSV_C128 ? 12 : 13, L = dtype == QSV_C128 ? 3 : 4;
-    {
-        key = shape_key(nb, nq, gate_off, g, term_off, qmasks, dtype);
-        qsv_status s = QSV_OK;
-        int tk = 0, tl = 0;
-        if (tune_lookup(ctx, key, dtype, &tk, &tl)) {
-            K = tk;
-            L = tl;
-        } else if (flags & QSV_FLAG_TUNE) {
-            // time each candidate once (every run computes the full, correct batch)
-            double best = 1e30;
-            for (const auto& sh : kTuneShapes) {
-                if (sh[0] >= 13 && dtype == QSV_C128) continue;   // not compiled (see launch_batch_k)
-                uint64_t k2 = 0;
-                BatchRun Rc;
-                s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
-                                sh[0], sh[1], Rc, k2);
-                if (s != QSV_OK) return s;
-                hipEvent_t e0, e1;
-                hipEventCreate(&e0);
-                hipEventCreate(&e1);
-                hipEventRecord(e0, ctx->stream);
-                hipError_t e = enqueue_batch(ctx, ctx->stream, dtype, sh[0], nb, Rc);
-                hipEventRecord(e1, ctx->stream);
-                if (e == hipSuccess) s = finish_batch(ctx, ctx->stream, nb, out);
-                float ms = 0.f;
-                if (e == hipSuccess && s == QSV_OK) hipEventElapsedTime(&ms, e0, e1);
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-                if (e != hipSuccess) {
-                    ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
+        if (dtype != QSV_C64 && dtype != QSV_C128) {
+            ctx->last_error = "qsv_batch_run: dtype must be QSV_C64 or QSV_C128";
+            return QSV_ERR_DTYPE;
+        }
+        if (nb < 1 || !nq || !gate_off || !term_off || !out || (nparams > 0 && !params) || nparams < 0) {
+            ctx->last_error = "qsv_batch_run: bad arguments";
+            return QSV_ERR_ARG;
+        }
+        if (flags & ~(QSV_FLAG_CAPTURE_GRAPH | QSV_FLAG_TUNE)) {
+            ctx->last_error = "qsv_batch_run: unknown flag";
+            return QSV_ERR_ARG;
+        }
+        for (int c = 0; c < nb; ++c) {
+            if (nq[c] < 1 || nq[c] > kMaxBatchQubits) {
+                ctx->last_error = "qsv_batch_run: circuit " + std::to_string(c) + " has " +
+                                  std::to_string(nq[c]) + " qubits (allowed 1.." +
+                                  std::to_string(kMaxBatchQubits) + ")";
+                return QSV_ERR_SIZE;
+            }
+            if (gate_off[c + 1] < gate_off[c] || term_off[c + 1] < term_off[c]) {
+                ctx->last_error = "qsv_batch_run: offsets must be non-decreasing";
+                return QSV_ERR_ARG;
+            }
+        }
+        if (gate_off[0] != 0 || term_off[0] != 0 || (gate_off[nb] > 0 && !g) || (term_off[nb] > 0 && !qmasks)) {
+            ctx->last_error = "qsv_batch_run: bad offsets or arrays";
+            return QSV_ERR_ARG;
+        }
+        // tile shape: the tuned choice for this batch shape, if any
+        BatchRun R;
+        uint64_t key = 0;
+        int K = dtype == QSV_C128 ? 12 : 13, L = dtype == QSV_C128 ? 3 : 4;
+        {
+            key = shape_key(nb, nq, gate_off, g, term_off, qmasks, dtype);
+            qsv_status s = QSV_OK;
+            int tk = 0, tl = 0;
+            if (tune_lookup(ctx, key, dtype, &tk, &tl)) {
+                K = tk;
+                L = tl;
+            } else if (flags & QSV_FLAG_TUNE) {
+                // time each candidate once (every run computes the full, correct batch)
+                double best = 1e30;
+                for (const auto& sh : kTuneShapes) {
+                    if (sh[0] >= 13 && dtype == QSV_C128) continue;   // not compiled (see launch_batch_k)
+                    uint64_t k2 = 0;
+                    BatchRun Rc;
+                    s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
+                                    sh[0], sh[1], Rc, k2);
+                    if (s != QSV_OK) return s;
+                    hipEvent_t e0, e1;
+                    hipEventCreate(&e0);
+                    hipEventCreate(&e1);
+                    hipEventRecord(e0, ctx->stream);
+                    hipError_t e = enqueue_batch(ctx, ctx->stream, dtype, sh[0], nb, Rc);
+                    hipEventRecord(e1, ctx->stream);
+                    if (e == hipSuccess) s = finish_batch(ctx, ctx->stream, nb, out);
+                    float ms = 0.f;
+                    if (e == hipSuccess && s == QSV_OK) hipEventElapsedTime(&ms, e0, e1);
+                    hipEventDestroy(e0);
+                    hipEventDestroy(e1);
+                    if (e != hipSuccess) {
+                        ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
+                        return QSV_ERR_HIP;
+                    }
+                    if (s != QSV_OK) return s;
+                    if (ms < best) {
+                        best = ms;
+                        K = sh[0];
+                        L = sh[1];
+                    }
+                }
+                tune_store(ctx, key, dtype, K, L, best);
+            }
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
+                                   dtype, K, L, R, key);
+        if (s != QSV_OK) return s;
+        if (log_enabled()) {
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            logf("batch: %d circuits, %d items, tile 2^%d low %d, plan %zu B, states %zu B, host planning %.2f ms",
+                 nb, R.nitems, K, L, R.L.total, R.state_bytes, ms);
+        }
+        hipError_t e;
+        if (flags & QSV_FLAG_CAPTURE_GRAPH) {
+            if (!ctx->batch_stream) {
+                if (hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking) != hipSuccess) {
+                    ctx->last_error = "qsv_batch_run: stream creation failed";
                     return QSV_ERR_HIP;
                 }
-                if (s != QSV_OK) return s;
-                if (ms < best) {
-                    best = ms;
-                    K = sh[0];
-                    L = sh[1];
+            }
+            const uint64_t gkey = key ^ (uint64_t(K) << 56) ^ (uint64_t(L) << 48) ^ uint64_t(R.L.total);
+            // order the batch after the context stream's earlier work
+            e = hipStreamSynchronize(ctx->stream);
+            if (e == hipSuccess && (!ctx->batch_graph_exec || ctx->batch_graph_key != gkey)) {
+                if (ctx->batch_graph_exec) {
+                    hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
+                    ctx->batch_graph_exec = nullptr;
+                }
+                hipGraph_t graph = nullptr;
+                e = hipStreamBeginCapture(ctx->batch_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    const bool prof = ctx->profiling;
+                    ctx->profiling = false;   // no event records inside the graph
+                    hipError_t e2 = enqueue_batch(ctx, ctx->batch_stream, dtype, K, nb, R);
+                    ctx->profiling = prof;
+                    e = hipStreamEndCapture(ctx->batch_stream, &graph);
+                    if (e2 != hipSuccess) e = e2;
+                }
+                hipGraphExec_t exec = nullptr;
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (graph) hipGraphDestroy(graph);
+                if (e == hipSuccess) {
+                    ctx->batch_graph_exec = exec;
+                    ctx->batch_graph_key = gkey;
                 }
             }
-            tune_store(ctx, key, dtype, K, L, best);
-        }
-    }
-    const auto t0 = std::chrono::steady_clock::now();
-    qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
-                               dtype, K, L, R, key);
-    if (s != QSV_OK) return s;
-    if (log_enabled()) {
-        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        logf("batch: %d circuits, %d items, tile 2^%d low %d, plan %zu B, states %zu B, host planning %.2f ms",
-             nb, R.nitems, K, L, R.L.total, R.state_bytes, ms);
-    }
-    hipError_t e;
-    if (flags & QSV_FLAG_CAPTURE_GRAPH) {
-        if (!ctx->batch_stream) {
-            if (hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking) != hipSuccess) {
-                ctx->last_error = "qsv_batch_run: stream creation failed";
+            if (e == hipSuccess) {
+                prof_before_on(ctx, ctx->batch_stream, dtype == QSV_C128 ? "batch_graph_c128" : "batch_graph_c64", 0.0);
+                e = hipGraphLaunch(static_cast<hipGraphExec_t>(ctx->batch_graph_exec), ctx->batch_stream);
+                prof_after_on(ctx, ctx->batch_stream);
+            }
+            if (e != hipSuccess) {
+                ctx->last_error = std::string("qsv_batch_run (graph): ") + hipGetErrorString(e);
                 return QSV_ERR_HIP;
             }
+            return finish_batch(ctx, ctx->batch_stream, nb, out);
         }
-        const uint64_t gkey = key ^ (uint64_t(K) << 56) ^ (uint64_t(L) << 48) ^ uint64_t(R.L.total);
-        // order the batch after the context stream's earlier work
-        e = hipStreamSynchronize(ctx->stream);
-        if (e == hipSuccess && (!ctx->batch_graph_exec || ctx->batch_graph_key != gkey)) {
-            if (ctx->batch_graph_exec) {
-                hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
-                ctx->batch_graph_exec = nullptr;
-            }
-            hipGraph_t graph = nullptr;
-            e = hipStreamBeginCapture(ctx->batch_stream, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                const bool prof = ctx->profiling;
-                ctx->profiling = false;   // no event records inside the graph
-                hipError_t e2 = enqueue_batch(ctx, ctx->batch_stream, dtype, K, nb, R);
-                ctx->profiling = prof;
-                e = hipStreamEndCapture(ctx->batch_stream, &graph);
-                if (e2 != hipSuccess) e = e2;
-            }
-            hipGraphExec_t exec = nullptr;
-            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (graph) hipGraphDestroy(graph);
-            if (e == hipSuccess) {
-                ctx->batch_graph_exec = exec;
-                ctx->batch_graph_key = gkey;
-            }
-        }
-        if (e == hipSuccess) {
-            prof_before_on(ctx, ctx->batch_stream, dtype == QSV_C128 ? "batch_graph_c128" : "batch_graph_c64", 0.0);
-            e = hipGraphLaunch(static_cast<hipGraphExec_t>(ctx->batch_graph_exec), ctx->batch_stream);
-            prof_after_on(ctx, ctx->batch_stream);
-        }
+        e = enqueue_batch(ctx, ctx->stream, dtype, K, nb, R);
         if (e != hipSuccess) {
-            ctx->last_error = std::string("qsv_batch_run (graph): ") + hipGetErrorString(e);
+            ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
             return QSV_ERR_HIP;
         }
-        return finish_batch(ctx, ctx->batch_stream, nb, out);
+        return finish_batch(ctx, ctx->stream, nb, out);
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    e = enqueue_batch(ctx, ctx->stream, dtype, K, nb, R);
-    if (e != hipSuccess) {
-        ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
-        return QSV_ERR_HIP;
-    }
-    return finish_batch(ctx, ctx->stream, nb, out);
 }

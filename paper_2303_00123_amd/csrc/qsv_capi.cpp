@@ -239,66 +239,90 @@ const char* qsv_status_str(qsv_status s) {
 const char* qsv_last_error(qsv_ctx ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
 qsv_status qsv_ctx_create(void* hip_stream, qsv_ctx* out) {
-    if (!out) return QSV_ERR_ARG;
-    *out = nullptr;
-    qsv_ctx ctx = new (std::nothrow) qsv_ctx_s();
-    if (!ctx) return QSV_ERR_NOMEM;
-    ctx->stream = static_cast<hipStream_t>(hip_stream);
-    hipError_t e = hipGetDevice(&ctx->device);
-    if (e == hipSuccess) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
-                hipSuccess && cus > 0)
-            ctx->num_cus = cus;
-        e = hipMalloc(reinterpret_cast<void**>(&ctx->d_red), kRedDoubles * sizeof(double));
+    try {
+        if (!out) return QSV_ERR_ARG;
+        *out = nullptr;
+        qsv_ctx ctx = new (std::nothrow) qsv_ctx_s();
+        if (!ctx) return QSV_ERR_NOMEM;
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+        hipError_t e = hipGetDevice(&ctx->device);
+        if (e == hipSuccess) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
+                    hipSuccess && cus > 0)
+                ctx->num_cus = cus;
+            e = hipMalloc(reinterpret_cast<void**>(&ctx->d_red), kRedDoubles * sizeof(double));
+        }
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_red), 4096, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->plan_copied, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ctx->plan_copied, ctx->stream);
+        if (e != hipSuccess) {
+            qsv_status st = e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP;
+            qsv_ctx_destroy(ctx);
+            return st;
+        }
+        *out = ctx;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_red), 4096, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->plan_copied, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(ctx->plan_copied, ctx->stream);
-    if (e != hipSuccess) {
-        qsv_status st = e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP;
-        qsv_ctx_destroy(ctx);
-        return st;
-    }
-    *out = ctx;
-    return QSV_OK;
 }
 
 qsv_status qsv_ctx_set_stream(qsv_ctx ctx, void* hip_stream) {
-    if (!ctx) return QSV_ERR_ARG;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (s == ctx->stream) return QSV_OK;
-    // order the old stream's outstanding work before anything on the new one
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    ctx->stream = s;
-    return QSV_OK;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (s == ctx->stream) return QSV_OK;
+        // order the old stream's outstanding work before anything on the new one
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        ctx->stream = s;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
-    if (!ctx) return QSV_ERR_ARG;
-    if (ctx->stream || ctx->d_red) hipStreamSynchronize(ctx->stream);
-    if (ctx->d_red) hipFree(ctx->d_red);
-    if (ctx->h_red) hipHostFree(ctx->h_red);
-    if (ctx->d_plan) hipFree(ctx->d_plan);
-    if (ctx->d_aux) hipFree(ctx->d_aux);
-    if (ctx->h_plan) hipHostFree(ctx->h_plan);
-    if (ctx->plan_copied) hipEventDestroy(ctx->plan_copied);
-    for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
-    if (ctx->batch_stream) hipStreamSynchronize(ctx->batch_stream);
-    if (ctx->batch_graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
-    if (ctx->d_batch) hipFree(ctx->d_batch);
-    if (ctx->h_batch) hipHostFree(ctx->h_batch);
-    if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
-    if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
-    delete ctx;
-    return QSV_OK;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        if (ctx->stream || ctx->d_red) hipStreamSynchronize(ctx->stream);
+        if (ctx->d_red) hipFree(ctx->d_red);
+        if (ctx->h_red) hipHostFree(ctx->h_red);
+        if (ctx->d_plan) hipFree(ctx->d_plan);
+        if (ctx->d_aux) hipFree(ctx->d_aux);
+        if (ctx->h_plan) hipHostFree(ctx->h_plan);
+        if (ctx->plan_copied) hipEventDestroy(ctx->plan_copied);
+        for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
+        if (ctx->batch_stream) hipStreamSynchronize(ctx->batch_stream);
+        if (ctx->batch_graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
+        if (ctx->d_batch) hipFree(ctx->d_batch);
+        if (ctx->h_batch) hipHostFree(ctx->h_batch);
+        if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
+        if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
+        delete ctx;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_sync(qsv_ctx ctx) {
-    if (!ctx) return QSV_ERR_ARG;
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return QSV_OK;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 // ------------------------------------------------------------------ states
@@ -310,123 +334,171 @@ static qsv_status check_n(qsv_ctx ctx, int n) {
 
 qsv_status qsv_state_wrap(qsv_ctx ctx, void* dev_ptr, size_t nbytes, int n, int dtype,
                           qsv_state* out) {
-    if (!ctx || !out) return QSV_ERR_ARG;
-    *out = nullptr;
-    if (!dev_ptr) return fail(ctx, QSV_ERR_ARG, "null device pointer");
-    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
-    if (qsv_status st = check_n(ctx, n)) return st;
-    if (reinterpret_cast<uintptr_t>(dev_ptr) % 16)
-        return fail(ctx, QSV_ERR_ALIGN, "device pointer must be 16-byte aligned");
-    const size_t need = (size_t(1) << n) * amp_bytes(dtype);
-    if (nbytes < need)
-        return fail(ctx, QSV_ERR_SIZE, "buffer holds " + std::to_string(nbytes) + " bytes, need " +
-                                           std::to_string(need));
-    qsv_state st = new (std::nothrow) qsv_state_s();
-    if (!st) return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
-    st->ctx = ctx;
-    st->ptr = dev_ptr;
-    st->n = n;
-    st->dtype = dtype;
-    st->owns = false;
-    st->nbytes = nbytes;
-    *out = st;
-    return QSV_OK;
+    try {
+        if (!ctx || !out) return QSV_ERR_ARG;
+        *out = nullptr;
+        if (!dev_ptr) return fail(ctx, QSV_ERR_ARG, "null device pointer");
+        if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+        if (qsv_status st = check_n(ctx, n)) return st;
+        if (reinterpret_cast<uintptr_t>(dev_ptr) % 16)
+            return fail(ctx, QSV_ERR_ALIGN, "device pointer must be 16-byte aligned");
+        const size_t need = (size_t(1) << n) * amp_bytes(dtype);
+        if (nbytes < need)
+            return fail(ctx, QSV_ERR_SIZE, "buffer holds " + std::to_string(nbytes) + " bytes, need " +
+                                               std::to_string(need));
+        qsv_state st = new (std::nothrow) qsv_state_s();
+        if (!st) return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
+        st->ctx = ctx;
+        st->ptr = dev_ptr;
+        st->n = n;
+        st->dtype = dtype;
+        st->owns = false;
+        st->nbytes = nbytes;
+        *out = st;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_state_alloc(qsv_ctx ctx, int n, int dtype, qsv_state* out) {
-    if (!ctx || !out) return QSV_ERR_ARG;
-    *out = nullptr;
-    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
-    if (qsv_status st = check_n(ctx, n)) return st;
-    if (qsv_status st = check_device(ctx)) return st;
-    const size_t need = (size_t(1) << n) * amp_bytes(dtype);
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, need);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, QSV_ERR_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    try {
+        if (!ctx || !out) return QSV_ERR_ARG;
+        *out = nullptr;
+        if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+        if (qsv_status st = check_n(ctx, n)) return st;
+        if (qsv_status st = check_device(ctx)) return st;
+        const size_t need = (size_t(1) << n) * amp_bytes(dtype);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, QSV_ERR_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+        }
+        qsv_state st = new (std::nothrow) qsv_state_s();
+        if (!st) {
+            hipFree(p);
+            return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
+        }
+        st->ctx = ctx;
+        st->ptr = p;
+        st->n = n;
+        st->dtype = dtype;
+        st->owns = true;
+        st->nbytes = need;
+        *out = st;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    qsv_state st = new (std::nothrow) qsv_state_s();
-    if (!st) {
-        hipFree(p);
-        return fail(ctx, QSV_ERR_NOMEM, "host allocation failed");
-    }
-    st->ctx = ctx;
-    st->ptr = p;
-    st->n = n;
-    st->dtype = dtype;
-    st->owns = true;
-    st->nbytes = need;
-    *out = st;
-    return QSV_OK;
 }
 
 qsv_status qsv_state_free(qsv_state st) {
-    if (!st) return QSV_ERR_ARG;
-    if (st->owns && st->ptr) {
-        hipStreamSynchronize(st->ctx->stream);
-        hipFree(st->ptr);
+    try {
+        if (!st) return QSV_ERR_ARG;
+        if (st->owns && st->ptr) {
+            hipStreamSynchronize(st->ctx->stream);
+            hipFree(st->ptr);
+        }
+        delete st;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    delete st;
-    return QSV_OK;
 }
 
 qsv_status qsv_state_info(qsv_state st, int* n, int* dtype, void** dev_ptr) {
-    if (!st) return QSV_ERR_ARG;
-    if (n) *n = st->n;
-    if (dtype) *dtype = st->dtype;
-    if (dev_ptr) *dev_ptr = st->ptr;
-    return QSV_OK;
+    try {
+        if (!st) return QSV_ERR_ARG;
+        if (n) *n = st->n;
+        if (dtype) *dtype = st->dtype;
+        if (dev_ptr) *dev_ptr = st->ptr;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_init_basis(qsv_state st, uint64_t b) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (b >= (uint64_t(1) << st->n)) return fail(ctx, QSV_ERR_ARG, "basis index >= 2^n");
-    HIP_OR_FAIL(ctx, launch_init_basis(ctx, st->ptr, st->n, st->dtype, b), "init_basis");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (b >= (uint64_t(1) << st->n)) return fail(ctx, QSV_ERR_ARG, "basis index >= 2^n");
+        HIP_OR_FAIL(ctx, launch_init_basis(ctx, st->ptr, st->n, st->dtype, b), "init_basis");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 // ------------------------------------------------------------------- gates
 qsv_status qsv_apply1q(qsv_state st, int q, const double* u) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
-    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
-    HIP_OR_FAIL(ctx, launch_apply1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), u), "apply1q");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+        if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+        HIP_OR_FAIL(ctx, launch_apply1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), u), "apply1q");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_applyC1q(qsv_state st, int qc, int qt, int ctrl_state, const double* u) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
-    if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "controlled gate needs n >= 2");
-    if (qc < 0 || qc >= st->n || qt < 0 || qt >= st->n)
-        return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
-    if (qc == qt) return fail(ctx, QSV_ERR_QUBIT, "control equals target");
-    if (ctrl_state != 0 && ctrl_state != 1)
-        return fail(ctx, QSV_ERR_ARG, "control state must be 0 or 1");
-    HIP_OR_FAIL(ctx,
-                launch_applyc1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qc),
-                                pos_of(st->n, qt), ctrl_state, u),
-                "applyC1q");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+        if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "controlled gate needs n >= 2");
+        if (qc < 0 || qc >= st->n || qt < 0 || qt >= st->n)
+            return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+        if (qc == qt) return fail(ctx, QSV_ERR_QUBIT, "control equals target");
+        if (ctrl_state != 0 && ctrl_state != 1)
+            return fail(ctx, QSV_ERR_ARG, "control state must be 0 or 1");
+        HIP_OR_FAIL(ctx,
+                    launch_applyc1q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qc),
+                                    pos_of(st->n, qt), ctrl_state, u),
+                    "applyC1q");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
-    if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "2-qubit gate needs n >= 2");
-    if (qa < 0 || qa >= st->n || qb < 0 || qb >= st->n)
-        return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
-    if (qa == qb) return fail(ctx, QSV_ERR_QUBIT, "repeated qubit");
-    HIP_OR_FAIL(ctx,
-                launch_apply2q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qa),
-                               pos_of(st->n, qb), u),
-                "apply2q");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+        if (st->n < 2) return fail(ctx, QSV_ERR_QUBIT, "2-qubit gate needs n >= 2");
+        if (qa < 0 || qa >= st->n || qb < 0 || qb >= st->n)
+            return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+        if (qa == qb) return fail(ctx, QSV_ERR_QUBIT, "repeated qubit");
+        HIP_OR_FAIL(ctx,
+                    launch_apply2q(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, qa),
+                                   pos_of(st->n, qb), u),
+                    "apply2q");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 static bool same_gates(const std::vector<PGate>& a, const std::vector<PGate>& b) {
@@ -480,184 +552,238 @@ static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<
 
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
-    if (nparams < 0) return fail(ctx, QSV_ERR_ARG, "negative parameter count");
-    if (flags & ~QSV_FLAG_NO_FUSE) return fail(ctx, QSV_ERR_ARG, "unknown flag");
-    std::vector<PGate> pg;
-    if (qsv_status s = lower(ctx, st->n, g, ng, params, nparams, pg)) return s;
-    if (pg.empty()) return QSV_OK;
-    if (flags & QSV_FLAG_NO_FUSE) {
-        for (const PGate& x : pg)
-            HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
+        if (nparams < 0) return fail(ctx, QSV_ERR_ARG, "negative parameter count");
+        if (flags & ~QSV_FLAG_NO_FUSE) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+        std::vector<PGate> pg;
+        if (qsv_status s = lower(ctx, st->n, g, ng, params, nparams, pg)) return s;
+        if (pg.empty()) return QSV_OK;
+        if (flags & QSV_FLAG_NO_FUSE) {
+            for (const PGate& x : pg)
+                HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
+            return QSV_OK;
+        }
+        HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg)), "tile passes");
         return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg)), "tile passes");
-    return QSV_OK;
 }
 
 // -------------------------------------------------------------- reductions
 qsv_status qsv_norm2(qsv_state st, double* out) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
-    const uint64_t zero = 0;
-    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, st->n, st->dtype, 1, &zero, out), "norm2");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
+        const uint64_t zero = 0;
+        HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, st->n, st->dtype, 1, &zero, out), "norm2");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_expect_z(qsv_state st, int nterms, const uint64_t* qmasks, const double* w,
                         double* out_terms, double* out_sum) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (nterms < 1 || nterms > 4096 || !qmasks)
-        return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
-    const int n = st->n;
-    std::vector<uint64_t> pm(size_t(nterms), 0);
-    for (int t = 0; t < nterms; ++t) {
-        if (n < 64 && (qmasks[t] >> n))
-            return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
-        for (int q = 0; q < n; ++q)
-            if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (nterms < 1 || nterms > 4096 || !qmasks)
+            return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
+        const int n = st->n;
+        std::vector<uint64_t> pm(size_t(nterms), 0);
+        for (int t = 0; t < nterms; ++t) {
+            if (n < 64 && (qmasks[t] >> n))
+                return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
+            for (int q = 0; q < n; ++q)
+                if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
+        }
+        std::vector<double> terms(size_t(nterms), 0.0);
+        HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, n, st->dtype, nterms, pm.data(), terms.data()),
+                    "expect_z");
+        double sum = 0.0;
+        for (int t = 0; t < nterms; ++t) sum += (w ? w[t] : 1.0) * terms[t];
+        if (out_terms) std::memcpy(out_terms, terms.data(), sizeof(double) * nterms);
+        if (out_sum) *out_sum = sum;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    std::vector<double> terms(size_t(nterms), 0.0);
-    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, st->ptr, n, st->dtype, nterms, pm.data(), terms.data()),
-                "expect_z");
-    double sum = 0.0;
-    for (int t = 0; t < nterms; ++t) sum += (w ? w[t] : 1.0) * terms[t];
-    if (out_terms) std::memcpy(out_terms, terms.data(), sizeof(double) * nterms);
-    if (out_sum) *out_sum = sum;
-    return QSV_OK;
 }
 
 qsv_status qsv_inner(qsv_state a, qsv_state b, double* out) {
-    if (qsv_status s = check_state(a)) return s;
-    if (!b) return QSV_ERR_ARG;
-    qsv_ctx ctx = a->ctx;
-    if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
-    if (a->n != b->n) return fail(ctx, QSV_ERR_SIZE, "states have different qubit counts");
-    if (b->ctx->device != ctx->device) return fail(ctx, QSV_ERR_ARG, "states on different devices");
-    if (b->ctx != ctx) HIP_OR_FAIL(ctx, hipStreamSynchronize(b->ctx->stream), "sync b");
-    HIP_OR_FAIL(ctx, reduce_inner(ctx, a->ptr, a->dtype, b->ptr, b->dtype, a->n, out), "inner");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(a)) return s;
+        if (!b) return QSV_ERR_ARG;
+        qsv_ctx ctx = a->ctx;
+        if (!out) return fail(ctx, QSV_ERR_ARG, "null output");
+        if (a->n != b->n) return fail(ctx, QSV_ERR_SIZE, "states have different qubit counts");
+        if (b->ctx->device != ctx->device) return fail(ctx, QSV_ERR_ARG, "states on different devices");
+        if (b->ctx != ctx) HIP_OR_FAIL(ctx, hipStreamSynchronize(b->ctx->stream), "sync b");
+        HIP_OR_FAIL(ctx, reduce_inner(ctx, a->ptr, a->dtype, b->ptr, b->dtype, a->n, out), "inner");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_prob1(qsv_state st, int q, double* p1) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!p1) return fail(ctx, QSV_ERR_ARG, "null output");
-    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
-    double r[2];
-    HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), r), "prob1");
-    *p1 = r[1];
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!p1) return fail(ctx, QSV_ERR_ARG, "null output");
+        if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+        double r[2];
+        HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos_of(st->n, q), r), "prob1");
+        *p1 = r[1];
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_measure1(qsv_state st, int q, double r, int* outcome) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    if (!outcome) return fail(ctx, QSV_ERR_ARG, "null output");
-    if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
-    if (!(r >= 0.0 && r < 1.0)) return fail(ctx, QSV_ERR_ARG, "r must lie in [0, 1)");
-    double p[2];
-    const int pos = pos_of(st->n, q);
-    HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos, p), "measure1");
-    int k = (r < p[0]) ? 0 : 1;
-    if (p[k] <= 0.0) k = 1 - k;   // r beyond a sub-unit total norm: take the other outcome
-    if (p[k] <= 0.0) return fail(ctx, QSV_ERR_ARG, "state has zero norm");
-    HIP_OR_FAIL(ctx, launch_collapse(ctx, st->ptr, st->n, st->dtype, pos, k, 1.0 / std::sqrt(p[k])),
-                "collapse");
-    *outcome = k;
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (!outcome) return fail(ctx, QSV_ERR_ARG, "null output");
+        if (q < 0 || q >= st->n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+        if (!(r >= 0.0 && r < 1.0)) return fail(ctx, QSV_ERR_ARG, "r must lie in [0, 1)");
+        double p[2];
+        const int pos = pos_of(st->n, q);
+        HIP_OR_FAIL(ctx, reduce_bit_split(ctx, st->ptr, st->n, st->dtype, pos, p), "measure1");
+        int k = (r < p[0]) ? 0 : 1;
+        if (p[k] <= 0.0) k = 1 - k;   // r beyond a sub-unit total norm: take the other outcome
+        if (p[k] <= 0.0) return fail(ctx, QSV_ERR_ARG, "state has zero norm");
+        HIP_OR_FAIL(ctx, launch_collapse(ctx, st->ptr, st->n, st->dtype, pos, k, 1.0 / std::sqrt(p[k])),
+                    "collapse");
+        *outcome = k;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_copy_to_host(qsv_state st, void* host, size_t nbytes) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
-    if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
-    if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(host, st->ptr, need, hipMemcpyDeviceToHost, ctx->stream),
-                "hipMemcpyAsync D2H");
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
+        if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
+        if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(host, st->ptr, need, hipMemcpyDeviceToHost, ctx->stream),
+                    "hipMemcpyAsync D2H");
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_copy_from_host(qsv_state st, const void* host, size_t nbytes) {
-    if (qsv_status s = check_state(st)) return s;
-    qsv_ctx ctx = st->ctx;
-    const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
-    if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
-    if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(st->ptr, host, need, hipMemcpyHostToDevice, ctx->stream),
-                "hipMemcpyAsync H2D");
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return QSV_OK;
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        const size_t need = (size_t(1) << st->n) * amp_bytes(st->dtype);
+        if (!host) return fail(ctx, QSV_ERR_ARG, "null host pointer");
+        if (nbytes < need) return fail(ctx, QSV_ERR_SIZE, "host buffer too small");
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(st->ptr, host, need, hipMemcpyHostToDevice, ctx->stream),
+                    "hipMemcpyAsync H2D");
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 // ------------------------------------------------------------------ adjoint
 qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t ng,
                        const double* params, int64_t nparams, int nterms, const uint64_t* qmasks,
                        const double* w, double* expval, double* grad, int flags) {
-    if (qsv_status s = check_state(psi)) return s;
-    qsv_ctx ctx = psi->ctx;
-    if (!lam || lam->ctx != ctx) return fail(ctx, QSV_ERR_ARG, "co-state must share the context");
-    if (lam->n != psi->n) return fail(ctx, QSV_ERR_SIZE, "co-state has a different qubit count");
-    if (lam->dtype != psi->dtype) return fail(ctx, QSV_ERR_DTYPE, "co-state has a different dtype");
-    if (lam->ptr == psi->ptr) return fail(ctx, QSV_ERR_ARG, "co-state aliases the state");
-    if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
-    if (nparams < 0 || (nparams > 0 && (!params || !grad)))
-        return fail(ctx, QSV_ERR_ARG, "bad parameter arrays");
-    if (nterms < 1 || nterms > 4096 || !qmasks)
-        return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
-    if (flags & ~(QSV_FLAG_FORWARD | QSV_FLAG_NO_FUSE)) return fail(ctx, QSV_ERR_ARG, "unknown flag");
-    const int n = psi->n;
-    std::vector<PGate> fwd;
-    if (qsv_status s = lower(ctx, n, g, ng, params, nparams, fwd)) return s;
-    std::vector<int> rot_param(size_t(ng), -1), rot_axis(size_t(ng), -1);
-    for (int64_t i = 0; i < ng; ++i)
-        if (g[i].kind == QSV_GROT) {
-            rot_param[size_t(i)] = g[i].param;
-            rot_axis[size_t(i)] = g[i].axis;
+    try {
+        if (qsv_status s = check_state(psi)) return s;
+        qsv_ctx ctx = psi->ctx;
+        if (!lam || lam->ctx != ctx) return fail(ctx, QSV_ERR_ARG, "co-state must share the context");
+        if (lam->n != psi->n) return fail(ctx, QSV_ERR_SIZE, "co-state has a different qubit count");
+        if (lam->dtype != psi->dtype) return fail(ctx, QSV_ERR_DTYPE, "co-state has a different dtype");
+        if (lam->ptr == psi->ptr) return fail(ctx, QSV_ERR_ARG, "co-state aliases the state");
+        if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
+        if (nparams < 0 || (nparams > 0 && (!params || !grad)))
+            return fail(ctx, QSV_ERR_ARG, "bad parameter arrays");
+        if (nterms < 1 || nterms > 4096 || !qmasks)
+            return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
+        if (flags & ~(QSV_FLAG_FORWARD | QSV_FLAG_NO_FUSE)) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+        const int n = psi->n;
+        std::vector<PGate> fwd;
+        if (qsv_status s = lower(ctx, n, g, ng, params, nparams, fwd)) return s;
+        std::vector<int> rot_param(size_t(ng), -1), rot_axis(size_t(ng), -1);
+        for (int64_t i = 0; i < ng; ++i)
+            if (g[i].kind == QSV_GROT) {
+                rot_param[size_t(i)] = g[i].param;
+                rot_axis[size_t(i)] = g[i].axis;
+            }
+        std::vector<uint64_t> pm(size_t(nterms), 0);
+        for (int t = 0; t < nterms; ++t) {
+            if (n < 64 && (qmasks[t] >> n))
+                return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
+            for (int q = 0; q < n; ++q)
+                if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
         }
-    std::vector<uint64_t> pm(size_t(nterms), 0);
-    for (int t = 0; t < nterms; ++t) {
-        if (n < 64 && (qmasks[t] >> n))
-            return fail(ctx, QSV_ERR_QUBIT, "term " + std::to_string(t) + " names a qubit >= n");
-        for (int q = 0; q < n; ++q)
-            if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
-    }
-    if (flags & QSV_FLAG_FORWARD) {
-        HIP_OR_FAIL(ctx, launch_init_basis(ctx, psi->ptr, n, psi->dtype, 0), "init");
-        if (!fwd.empty()) {
-            if (flags & QSV_FLAG_NO_FUSE) {
-                for (const PGate& x : fwd)
-                    HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
-            } else {
-                HIP_OR_FAIL(ctx, run_fused(ctx, psi->ptr, n, psi->dtype, std::vector<PGate>(fwd)),
-                            "forward passes");
+        if (flags & QSV_FLAG_FORWARD) {
+            HIP_OR_FAIL(ctx, launch_init_basis(ctx, psi->ptr, n, psi->dtype, 0), "init");
+            if (!fwd.empty()) {
+                if (flags & QSV_FLAG_NO_FUSE) {
+                    for (const PGate& x : fwd)
+                        HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
+                } else {
+                    HIP_OR_FAIL(ctx, run_fused(ctx, psi->ptr, n, psi->dtype, std::vector<PGate>(fwd)),
+                                "forward passes");
+                }
             }
         }
+        std::vector<double> terms(size_t(nterms), 0.0);
+        HIP_OR_FAIL(ctx, reduce_zstrings(ctx, psi->ptr, n, psi->dtype, nterms, pm.data(), terms.data()),
+                    "expectation");
+        double f = 0.0;
+        for (int t = 0; t < nterms; ++t) f += (w ? w[t] : 1.0) * terms[size_t(t)];
+        std::vector<double> wv(size_t(nterms), 1.0);
+        if (w) std::memcpy(wv.data(), w, sizeof(double) * nterms);
+        std::vector<double> by_gate(size_t(ng), 0.0);
+        HIP_OR_FAIL(ctx,
+                    run_adjoint(ctx, psi->ptr, lam->ptr, n, psi->dtype, fwd, rot_param, rot_axis,
+                                nterms, pm.data(), wv.data(), by_gate.data(),
+                                !(flags & QSV_FLAG_NO_FUSE)),
+                    "adjoint sweep");
+        for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
+        for (int64_t i = 0; i < ng; ++i)
+            if (rot_param[size_t(i)] >= 0) grad[rot_param[size_t(i)]] += by_gate[size_t(i)];
+        if (expval) *expval = f;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    std::vector<double> terms(size_t(nterms), 0.0);
-    HIP_OR_FAIL(ctx, reduce_zstrings(ctx, psi->ptr, n, psi->dtype, nterms, pm.data(), terms.data()),
-                "expectation");
-    double f = 0.0;
-    for (int t = 0; t < nterms; ++t) f += (w ? w[t] : 1.0) * terms[size_t(t)];
-    std::vector<double> wv(size_t(nterms), 1.0);
-    if (w) std::memcpy(wv.data(), w, sizeof(double) * nterms);
-    std::vector<double> by_gate(size_t(ng), 0.0);
-    HIP_OR_FAIL(ctx,
-                run_adjoint(ctx, psi->ptr, lam->ptr, n, psi->dtype, fwd, rot_param, rot_axis,
-                            nterms, pm.data(), wv.data(), by_gate.data(),
-                            !(flags & QSV_FLAG_NO_FUSE)),
-                "adjoint sweep");
-    for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
-    for (int64_t i = 0; i < ng; ++i)
-        if (rot_param[size_t(i)] >= 0) grad[rot_param[size_t(i)]] += by_gate[size_t(i)];
-    if (expval) *expval = f;
-    return QSV_OK;
 }
 
 // ------------------------------------------------------------------ tuning
@@ -690,146 +816,176 @@ static qsv_status tile_config(int dtype, int tile_bits, int low_bits, int reg_bi
 
 qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits,
                         int lds_rounds) {
-    if (!ctx) return QSV_ERR_ARG;
-    if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
-    std::string err;
-    TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err))
-        return fail(ctx, s, err);
-    (dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64) = cfg;
-    return QSV_OK;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        if (!valid_dtype(dtype)) return fail(ctx, QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+        std::string err;
+        TileConfig cfg{};
+        if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err))
+            return fail(ctx, s, err);
+        (dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64) = cfg;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_plan_circuit(int n, int dtype, const qsv_gate* g, int64_t ng, int tile_bits,
                             int low_bits, int reg_bits, int64_t* npasses, int32_t* pass_of_gate,
                             int32_t* exec_order, uint64_t* pass_qubits) {
-    if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
-    if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
-    if (ng < 0 || (ng > 0 && (!g || !pass_of_gate || !exec_order || !pass_qubits)) || !npasses)
-        return QSV_ERR_ARG;
-    std::string err;
-    TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, 0, cfg, err)) return s;
-    // positions only: rotations get a placeholder angle
-    std::vector<double> zeros(size_t(ng) + 1, 0.0);
-    std::vector<qsv_gate> gg(g, g + ng);
-    for (auto& x : gg)
-        if (x.kind == QSV_GROT) x.param = 0;
-    std::vector<PGate> pg;
-    if (qsv_status s = lower(nullptr, n, gg.data(), ng, zeros.data(), 1, pg)) return s;
-    std::vector<Pass> passes = plan_passes(n, pg, cfg);
-    int64_t k = 0;
-    for (size_t p = 0; p < passes.size(); ++p) {
-        uint64_t qm = 0;
-        for (int b = 0; b < passes[p].k; ++b) qm |= uint64_t(1) << pos_of(n, passes[p].pos[b]);
-        pass_qubits[p] = qm;
-        for (int gi : passes[p].gates) pass_of_gate[gi] = int32_t(p);
-        if (passes[p].single || passes[p].stages.empty()) {
-            for (int gi : passes[p].gates) exec_order[k++] = gi;
-        } else {
-            for (const Stage& st : passes[p].stages)
-                for (int gi : st.gates) exec_order[k++] = gi;
+    try {
+        if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
+        if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
+        if (ng < 0 || (ng > 0 && (!g || !pass_of_gate || !exec_order || !pass_qubits)) || !npasses)
+            return QSV_ERR_ARG;
+        std::string err;
+        TileConfig cfg{};
+        if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, 0, cfg, err)) return s;
+        // positions only: rotations get a placeholder angle
+        std::vector<double> zeros(size_t(ng) + 1, 0.0);
+        std::vector<qsv_gate> gg(g, g + ng);
+        for (auto& x : gg)
+            if (x.kind == QSV_GROT) x.param = 0;
+        std::vector<PGate> pg;
+        if (qsv_status s = lower(nullptr, n, gg.data(), ng, zeros.data(), 1, pg)) return s;
+        std::vector<Pass> passes = plan_passes(n, pg, cfg);
+        int64_t k = 0;
+        for (size_t p = 0; p < passes.size(); ++p) {
+            uint64_t qm = 0;
+            for (int b = 0; b < passes[p].k; ++b) qm |= uint64_t(1) << pos_of(n, passes[p].pos[b]);
+            pass_qubits[p] = qm;
+            for (int gi : passes[p].gates) pass_of_gate[gi] = int32_t(p);
+            if (passes[p].single || passes[p].stages.empty()) {
+                for (int gi : passes[p].gates) exec_order[k++] = gi;
+            } else {
+                for (const Stage& st : passes[p].stages)
+                    for (int gi : st.gates) exec_order[k++] = gi;
+            }
         }
+        *npasses = int64_t(passes.size());
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    *npasses = int64_t(passes.size());
-    return QSV_OK;
 }
 
 qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
                           int64_t nparams, int tile_bits, int low_bits, int reg_bits, int lds_rounds,
                           qsv_gate* out, int64_t cap, int32_t* pass_of_out, int64_t* nout) {
-    if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
-    if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
-    if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
-    std::string err;
-    TileConfig cfg{};
-    if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err)) return s;
-    std::vector<PGate> pg;
-    if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
-    if (n >= kMinTileBits) pg = prefuse(pg);
-    std::vector<Pass> passes = plan_passes(n, pg, cfg);
-    {
-        std::vector<char> rec;
-        for (const Pass& ps : passes) {
-            if (ps.single || ps.stages.empty()) continue;
-            rec.assign(pass_record_bytes(dtype, ps), 0);
-            if (!write_pass_record(dtype, rec.data(), pg, ps)) return QSV_ERR_INTERNAL;
-        }
-    }
-    int64_t k = 0;
-    auto emit = [&](const PGate& x, int32_t p) {
-        if (k < cap) {
-            qsv_gate o{};
-            o.kind = x.kind;
-            o.q0 = pos_of(n, x.p0);
-            o.q1 = x.kind == QSV_G1Q ? 0 : pos_of(n, x.p1);
-            o.ctrl_state = x.cs;
-            o.param = -1;
-            std::memcpy(o.m, x.m, sizeof(o.m));
-            if (out) out[k] = o;
-            if (pass_of_out) pass_of_out[k] = p;
-        }
-        ++k;
-    };
-    for (size_t p = 0; p < passes.size(); ++p) {
-        const Pass& ps = passes[p];
-        if (ps.single || ps.stages.empty()) {
-            for (int gi : ps.gates) emit(pg[size_t(gi)], int32_t(p));
-            logf("plan: pass %zu single gate", p);
-        } else {
-            std::string st_desc;
-            size_t nf = 0;
-            for (const Stage& st : ps.stages) {
-                const std::vector<PGate> f = fuse_stage(pg, st.gates);
-                for (const PGate& x : f) emit(x, int32_t(p));
-                nf += f.size();
-                st_desc += " " + std::to_string(f.size());
+    try {
+        if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
+        if (n < 1 || n > kMaxQubits) return QSV_ERR_SIZE;
+        if (ng < 0 || (ng > 0 && !g) || !nout || cap < 0) return QSV_ERR_ARG;
+        std::string err;
+        TileConfig cfg{};
+        if (qsv_status s = tile_config(dtype, tile_bits, low_bits, reg_bits, lds_rounds, cfg, err)) return s;
+        std::vector<PGate> pg;
+        if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
+        if (n >= kMinTileBits) pg = prefuse(pg);
+        std::vector<Pass> passes = plan_passes(n, pg, cfg);
+        {
+            std::vector<char> rec;
+            for (const Pass& ps : passes) {
+                if (ps.single || ps.stages.empty()) continue;
+                rec.assign(pass_record_bytes(dtype, ps), 0);
+                if (!write_pass_record(dtype, rec.data(), pg, ps)) return QSV_ERR_INTERNAL;
             }
-            logf("plan: pass %zu: %zu gates -> %zu fused, %zu stages (fused gates per stage:%s)", p,
-                 ps.gates.size(), nf, ps.stages.size(), st_desc.c_str());
         }
+        int64_t k = 0;
+        auto emit = [&](const PGate& x, int32_t p) {
+            if (k < cap) {
+                qsv_gate o{};
+                o.kind = x.kind;
+                o.q0 = pos_of(n, x.p0);
+                o.q1 = x.kind == QSV_G1Q ? 0 : pos_of(n, x.p1);
+                o.ctrl_state = x.cs;
+                o.param = -1;
+                std::memcpy(o.m, x.m, sizeof(o.m));
+                if (out) out[k] = o;
+                if (pass_of_out) pass_of_out[k] = p;
+            }
+            ++k;
+        };
+        for (size_t p = 0; p < passes.size(); ++p) {
+            const Pass& ps = passes[p];
+            if (ps.single || ps.stages.empty()) {
+                for (int gi : ps.gates) emit(pg[size_t(gi)], int32_t(p));
+                logf("plan: pass %zu single gate", p);
+            } else {
+                std::string st_desc;
+                size_t nf = 0;
+                for (const Stage& st : ps.stages) {
+                    const std::vector<PGate> f = fuse_stage(pg, st.gates);
+                    for (const PGate& x : f) emit(x, int32_t(p));
+                    nf += f.size();
+                    st_desc += " " + std::to_string(f.size());
+                }
+                logf("plan: pass %zu: %zu gates -> %zu fused, %zu stages (fused gates per stage:%s)", p,
+                     ps.gates.size(), nf, ps.stages.size(), st_desc.c_str());
+            }
+        }
+        *nout = k;
+        return k > cap ? QSV_ERR_SIZE : QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    *nout = k;
-    return k > cap ? QSV_ERR_SIZE : QSV_OK;
 }
 
 // ---------------------------------------------------------------- profiling
 qsv_status qsv_profile_begin(qsv_ctx ctx) {
-    if (!ctx) return QSV_ERR_ARG;
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    ctx->prof.clear();
-    ctx->event_next = 0;
-    ctx->profiling = true;
-    return QSV_OK;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        ctx->prof.clear();
+        ctx->event_next = 0;
+        ctx->profiling = true;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
 }
 
 qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count) {
-    if (!ctx) return QSV_ERR_ARG;
-    ctx->profiling = false;
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    std::map<std::string, qsv_kstat> agg;
-    for (const ProfRec& r : ctx->prof) {
-        float ms = 0.f;
-        HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, r.start, r.stop), "hipEventElapsedTime");
-        qsv_kstat& k = agg[r.name];
-        k.launches += 1;
-        k.ms += ms;
-        k.bytes += r.bytes;
-    }
-    int i = 0;
-    for (auto& kv : agg) {
-        if (out && i < max) {
-            qsv_kstat k = kv.second;
-            std::memset(k.name, 0, sizeof(k.name));
-            std::strncpy(k.name, kv.first.c_str(), sizeof(k.name) - 1);
-            out[i] = k;
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        ctx->profiling = false;
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        std::map<std::string, qsv_kstat> agg;
+        for (const ProfRec& r : ctx->prof) {
+            float ms = 0.f;
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, r.start, r.stop), "hipEventElapsedTime");
+            qsv_kstat& k = agg[r.name];
+            k.launches += 1;
+            k.ms += ms;
+            k.bytes += r.bytes;
         }
-        ++i;
+        int i = 0;
+        for (auto& kv : agg) {
+            if (out && i < max) {
+                qsv_kstat k = kv.second;
+                std::memset(k.name, 0, sizeof(k.name));
+                std::strncpy(k.name, kv.first.c_str(), sizeof(k.name) - 1);
+                out[i] = k;
+            }
+            ++i;
+        }
+        if (count) *count = i;
+        ctx->prof.clear();
+        ctx->event_next = 0;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
     }
-    if (count) *count = i;
-    ctx->prof.clear();
-    ctx->event_next = 0;
-    return QSV_OK;
 }
 
 }  // extern "C"

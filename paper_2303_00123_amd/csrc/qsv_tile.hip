@@ -62,11 +62,16 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
     V* const sp = s + (b | deposit(tid, hdr->tpos_ld, TB));
 
+    // memory and LDS phases run at raised wave priority, so the other
+    // resident workgroup's arithmetic fills the gaps instead of delaying them
     V v[P];
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int u = 0; u < P; ++u) v[u] = ld_nt(sp + hdr->du[u]);
+    __builtin_amdgcn_s_setprio(0);
     run_stages<R, K, RB, SPLIT>(v, lds, stg, nst, gates, tid);
     V* const sq = s + (b | deposit(tid, hdr->tpos_st, TB));
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int u = 0; u < P; ++u) st_nt(sq + hdr->du_st[u], v[u]);
 }

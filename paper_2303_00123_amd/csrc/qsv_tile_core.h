@@ -324,6 +324,7 @@ __device__ __forceinline__ void run_stages(V (&v)[1 << RB], char* lds, const TSt
                 const uint32_t sbw = swz<R>(deposit32(tid, S.tbw, TB)) * ES;
                 const uint32_t sbr = swz<R>(deposit32(tid, N.tbr, TB)) * ES;
                 V w[P / 2];
+                __builtin_amdgcn_s_setprio(2);   // LDS phase (see the tile kernel)
                 if (st > 0) lds_barrier();   // the previous change's reads are done
                 write_half<RB, 0>(v, lds, sbw, S.su_wr, S.jw);
                 lds_barrier();
@@ -336,6 +337,7 @@ __device__ __forceinline__ void run_stages(V (&v)[1 << RB], char* lds, const TSt
                 for (int u = P / 2; u < P; ++u) v[u] = *reinterpret_cast<const V*>(lds + (sbr ^ N.su[u]));
 #pragma unroll
                 for (int u = 0; u < P / 2; ++u) v[u] = w[u];
+                __builtin_amdgcn_s_setprio(0);
             }
         }
     }

@@ -119,47 +119,62 @@ __device__ __forceinline__ double rot_part(const V (&v)[P], const V (&l)[P]) {
     return acc;
 }
 
-// (dv, dl) = gate(sv, sl) on both vectors; a rotation also emits its
-// partial Im<lam|P|psi> (taken before the rotation is undone).  `copy`
-// makes it the identity.
-template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_gate2(const V (&sv)[P], V (&dv)[P], const V (&sl)[P], V (&dl)[P],
-                                            const TGate<R>& g, bool copy, double* __restrict__ part_out,
-                                            uint32_t tid) {
-    if (!copy && g.kind == DK_ROT) {
+// Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
+// traffic, short dependent latency); the total lands in lane 63.  Lanes a
+// move reads from outside the row, or rows the row mask leaves out, add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_to_lane63(double s) {
+    s += dpp_move<0x111, 0xf>(s);   // row_shr:1
+    s += dpp_move<0x112, 0xf>(s);   // row_shr:2
+    s += dpp_move<0x114, 0xf>(s);   // row_shr:4
+    s += dpp_move<0x118, 0xf>(s);   // row_shr:8: lane 15 of each row holds the row sum
+    s += dpp_move<0x142, 0xa>(s);   // row_bcast:15 into rows 1 and 3
+    s += dpp_move<0x143, 0xc>(s);   // row_bcast:31 into rows 2 and 3
+    return s;
+}
+
+// The gate on both vectors, in place; a rotation also emits its partial
+// Im<lam|P|psi> (taken before the rotation is undone).  SPEC selects the
+// rotation bodies that use the structure of the axis.
+template <int RB, bool SPEC, typename R, typename V, int P>
+__device__ __forceinline__ void apply_gate2(V (&v)[P], V (&l)[P], const TGate<R>& g,
+                                            double* __restrict__ part_out, uint32_t tid) {
+    if (g.kind == DK_ROT) {
         double part = 0.0;
         on_bit<RB>(g.r0, [&](auto B) __attribute__((always_inline)) {
             constexpr int b = decltype(B)::value;
             // the rewind exp(+i theta P / 2) has the structure of its axis:
-            // X -> [[c, i s], [i s, c]], Y -> real, Z -> diagonal.  The
-            // complex64 kernel keeps the generic body: the three specialised
-            // ones push it past 256 registers (one wave per SIMD).
-            if constexpr (sizeof(R) == 4) {
-                if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(sv, sl);
-                else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(sv, sl);
-                else part = rot_part<b, QSV_AXIS_Z>(sv, sl);
-                rg_1q<b>(sv, dv, g.m);
-                rg_1q<b>(sl, dl, g.m);
+            // X -> [[c, i s], [i s, c]], Y -> real, Z -> diagonal
+            if constexpr (!SPEC) {
+                if (g.cs == QSV_AXIS_X) part = rot_part<b, QSV_AXIS_X>(v, l);
+                else if (g.cs == QSV_AXIS_Y) part = rot_part<b, QSV_AXIS_Y>(v, l);
+                else part = rot_part<b, QSV_AXIS_Z>(v, l);
+                rg_1q<b>(v, v, g.m);
+                rg_1q<b>(l, l, g.m);
             } else if (g.cs == QSV_AXIS_X) {
-                part = rot_part<b, QSV_AXIS_X>(sv, sl);
-                rg_1x<b>(sv, dv, g.m);
-                rg_1x<b>(sl, dl, g.m);
+                part = rot_part<b, QSV_AXIS_X>(v, l);
+                rg_1x<b>(v, v, g.m);
+                rg_1x<b>(l, l, g.m);
             } else if (g.cs == QSV_AXIS_Y) {
-                part = rot_part<b, QSV_AXIS_Y>(sv, sl);
-                rg_1r<b>(sv, dv, g.m);
-                rg_1r<b>(sl, dl, g.m);
+                part = rot_part<b, QSV_AXIS_Y>(v, l);
+                rg_1r<b>(v, v, g.m);
+                rg_1r<b>(l, l, g.m);
             } else {
-                part = rot_part<b, QSV_AXIS_Z>(sv, sl);
-                rg_1d<b>(sv, dv, g.m + 8);
-                rg_1d<b>(sl, dl, g.m + 8);
+                part = rot_part<b, QSV_AXIS_Z>(v, l);
+                rg_1d<b>(v, v, g.m + 8);
+                rg_1d<b>(l, l, g.m + 8);
             }
         });
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-        if ((tid & 63) == 0) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
+        part = wave_sum_to_lane63(part);
+        if ((tid & 63) == 63) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
     } else {
-        const int op = copy ? kOpCopy : g.kind * 64 + g.r0 * 8 + g.r1;
-        apply_op<RB>(sv, dv, op, g.m);
-        apply_op<RB>(sl, dl, op, g.m);
+        apply_op2_inplace<RB>(v, l, g.kind * 64 + g.r0 * 8 + g.r1, g.m);
     }
 }
 
@@ -168,7 +183,7 @@ __device__ __forceinline__ void apply_gate2(const V (&sv)[P], V (&dv)[P], const 
 // SPLIT: consecutive stages share a register bit and each vector changes
 // mapping in two half-tile rounds through LDS (see run_stages), so the two
 // tiles take half the LDS.
-template <typename R, int K, bool SPLIT>
+template <typename R, int K, bool SPLIT, bool SPEC>
 __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __restrict__ psi,
                                                        typename V2T<R>::type* __restrict__ lam,
                                                        const char* __restrict__ plan,
@@ -214,15 +229,9 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
                 l[u] = *reinterpret_cast<const V*>(ll + (sb ^ S.su[u]));
             }
         }
-        {
-            // two gates per iteration, alternating register sets (no copies)
-            V vw[P], lw[P];
-            for (int g = S.gbeg; g < S.gend; g += 2) {
-                apply_gate2<RB>(v, vw, l, lw, gates[g], false, part_out, tid);
-                const bool two = g + 1 < S.gend;
-                apply_gate2<RB>(vw, v, lw, l, gates[two ? g + 1 : g], !two, part_out, tid);
-            }
-        }
+        // in place: two register sets per vector (as in the one-state
+        // kernel) would double the registers and halve the occupancy
+        for (int g = S.gbeg; g < S.gend; ++g) apply_gate2<RB, SPEC>(v, l, gates[g], part_out, tid);
         if (!SPLIT && st < nst - 1) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
@@ -289,18 +298,30 @@ __global__ __launch_bounds__(kThreads) void k_adj_cols(const double* __restrict_
     if (threadIdx.x == 0) grad[tags[s]] = tot[0];
 }
 
-template <typename R, int K>
+// Two-vector tile shape per precision (measured on a 24-qubit, 480-angle
+// circuit).  complex128: 2^11 amplitudes with split exchange, 32 KiB of LDS
+// and about 135 registers, so three workgroups fit per CU.  complex64: 2^12
+// amplitudes with full exchange (64 KiB, two per CU); its split variant
+// is no faster, being register-bound at two waves per SIMD either way.
+// The axis-specialised rotation bodies push the complex64 kernel past 256
+// registers (one wave per SIMD), so it keeps the generic 2x2 body.
+template <typename R>
+struct AdjShape {
+    static constexpr int K = sizeof(R) == 8 ? 11 : 12;
+    static constexpr bool SPLIT = sizeof(R) == 8;
+    static constexpr bool SPEC = sizeof(R) == 8;
+};
+
+template <typename R>
 hipError_t launch_adj_tile(qsv_ctx ctx, void* psi, void* lam, int n, const char* rec,
                            double* partials) {
     using V = typename V2T<R>::type;
-    const unsigned tiles = unsigned(uint64_t(1) << (n - K));
-    hipLaunchKernelGGL((k_adj_tile<R, K, false>), dim3(tiles), dim3(kThreads), 0, ctx->stream,
-                       static_cast<V*>(psi), static_cast<V*>(lam), rec, partials);
+    using S = AdjShape<R>;
+    const unsigned tiles = unsigned(uint64_t(1) << (n - S::K));
+    hipLaunchKernelGGL((k_adj_tile<R, S::K, S::SPLIT, S::SPEC>), dim3(tiles), dim3(kThreads), 0,
+                       ctx->stream, static_cast<V*>(psi), static_cast<V*>(lam), rec, partials);
     return hipGetLastError();
 }
-
-template <typename R>
-constexpr int adj_tile_bits() { return sizeof(R) == 8 ? 11 : 12; }   // two tiles: 64 KiB of LDS
 
 void dagger(const PGate& g, PGate& d) {
     d = g;
@@ -365,7 +386,7 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
     const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
     const uint64_t N = uint64_t(1) << n;
     const size_t ng = fwd.size();
-    constexpr int KA = adj_tile_bits<R>();
+    constexpr int KA = AdjShape<R>::K;
     if (n < KA) fused = false;
 
     // observable upload: masks then weights
@@ -416,7 +437,8 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
         }
         rev = prefuse(rev);
         std::vector<Pass> passes =
-            plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt), 0});
+            plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt),
+                                         AdjShape<R>::SPLIT ? 1 : 0});
         // slots, record layout, partial-buffer size
         size_t bytes = 0, max_part = 0;
         std::vector<size_t> offs(passes.size(), 0), tag_off(passes.size(), 0);
@@ -474,7 +496,7 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
             }
             prof_before(ctx, sizeof(R) == 8 ? "adj_tile_c128" : "adj_tile_c64",
                         4.0 * double(N) * sizeof(V));
-            e = launch_adj_tile<R, KA>(ctx, psi, lam, n, drec + offs[i], dpart);
+            e = launch_adj_tile<R>(ctx, psi, lam, n, drec + offs[i], dpart);
             prof_after(ctx);
             if (e != hipSuccess) return e;
             if (nslot[i] > 0) {

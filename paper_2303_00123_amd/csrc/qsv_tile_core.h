@@ -55,7 +55,10 @@ __device__ __forceinline__ void lds_barrier() {
 // ---------------------------------------------------- register gate bodies
 // Each body reads the amplitudes from s and writes every slot of d (slots
 // the gate leaves alone are copied), so results never overwrite inputs that
-// are still live and need no register copies afterwards.
+// are still live and need no register copies afterwards.  Every body reads
+// the amplitudes of a pair or quad before it writes them, so s and d may
+// also be the same array (in-place update); the CNOT body needs to know
+// which, because its two forms differ (a renaming, or a swap in place).
 template <int B, typename R, typename V, int P>
 __device__ __forceinline__ void rg_1q(const V (&s)[P], V (&d)[P], const R* m) {
 #pragma unroll
@@ -121,10 +124,18 @@ __device__ __forceinline__ void rg_c1q(const V (&s)[P], V (&d)[P], const R* m) {
     }
 }
 
-template <int C, int T, typename V, int P>
+template <int C, int T, bool INPL, typename V, int P>
 __device__ __forceinline__ void rg_cx(const V (&s)[P], V (&d)[P]) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) d[i] = ((i >> C) & 1) ? s[i ^ (1 << T)] : s[i];
+    for (int i = 0; i < P; ++i) {
+        if constexpr (!INPL) {
+            d[i] = ((i >> C) & 1) ? s[i ^ (1 << T)] : s[i];
+        } else if (((i >> C) & 1) && !(i & (1 << T))) {   // s is d: swap the pair
+            const V a = s[i], b = s[i | (1 << T)];
+            d[i] = b;
+            d[i | (1 << T)] = a;
+        }
+    }
 }
 
 template <int C, int T, typename R, typename V, int P>
@@ -191,7 +202,7 @@ __device__ __forceinline__ void on_bit(int b, F&& f) {
     case (KD) * 64 + (A) * 8 + (B):                                            \
         if constexpr ((A) < RB && (B) < RB && (A) != (B) && ((KD) != DK_2Q || (A) < (B))) { \
             if constexpr ((KD) == DK_2Q) QSV_EACH(rg_2q<(A), (B)>(s, d, m));   \
-            else if constexpr ((KD) == DK_CX) QSV_EACH(rg_cx<(A), (B)>(s, d)); \
+            else if constexpr ((KD) == DK_CX) QSV_EACH(rg_cx<(A), (B), INPL>(s, d)); \
             else if constexpr ((KD) == DK_CD) QSV_EACH(rg_cd<(A), (B)>(s, d, m)); \
             else QSV_EACH(rg_c1q<(A), (B)>(s, d, m));                          \
         } else {                                                               \
@@ -213,7 +224,7 @@ __device__ __forceinline__ void copy_regs(const V (&s)[P], V (&d)[P]) {
     for (int u = 0; u < P; ++u) d[u] = s[u];
 }
 
-template <int RB, typename R, typename EACH>
+template <int RB, bool INPL, typename R, typename EACH>
 __device__ __forceinline__ void apply_op_each(int op, const R* m, EACH&& each) {
     switch (op) {
     case kOpCopy:
@@ -232,16 +243,16 @@ __device__ __forceinline__ void apply_op_each(int op, const R* m, EACH&& each) {
 
 template <int RB, typename R, typename V, int P>
 __device__ __forceinline__ void apply_op(const V (&s)[P], V (&d)[P], int op, const R* m) {
-    apply_op_each<RB>(op, m, [&](auto&& f) __attribute__((always_inline)) { f(s, d); });
+    apply_op_each<RB, false>(op, m, [&](auto&& f) __attribute__((always_inline)) { f(s, d); });
 }
 
-// The same gate on two states (the adjoint sweep's state and co-state).
+// The same gate on two states (the adjoint sweep's state and co-state),
+// each updated in place.
 template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_op2(const V (&s1)[P], V (&d1)[P], const V (&s2)[P], V (&d2)[P],
-                                          int op, const R* m) {
-    apply_op_each<RB>(op, m, [&](auto&& f) __attribute__((always_inline)) {
-        f(s1, d1);
-        f(s2, d2);
+__device__ __forceinline__ void apply_op2_inplace(V (&v1)[P], V (&v2)[P], int op, const R* m) {
+    apply_op_each<RB, true>(op, m, [&](auto&& f) __attribute__((always_inline)) {
+        f(v1, v1);
+        f(v2, v2);
     });
 }
 

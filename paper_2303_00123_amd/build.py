@@ -37,7 +37,8 @@ SOURCES = [
 #   index maps live in switch cases; sinking their common code would turn the
 #   constant indices into a runtime-selected one and push the per-thread
 #   amplitude array out of registers into scratch memory.
-# kernel-resource-usage remarks are parsed to reject any kernel that spills.
+# kernel-resource-usage remarks are parsed to reject any kernel that spills
+# to scratch or overflows into accumulation registers (see _compile).
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -63,6 +64,14 @@ def _compile(src: str) -> str:
     spills = {k: v for k, v in usage.items() if v.get("ScratchSize [bytes/lane]", 0) > 0}
     if spills:
         raise RuntimeError(f"{src}: kernels use scratch memory: {sorted(spills)}")
+    # No kernel here uses matrix instructions, so accumulation registers in
+    # use mean the arrays overflowed 256 vector registers: the kernel then
+    # runs one wave per SIMD.  That is accepted only where LDS already
+    # limits it to one workgroup per CU (more than 80 KiB).
+    overflow = {k for k, v in usage.items()
+                if v.get("AGPRs", 0) > 0 and v.get("LDS Size [bytes/block]", 0) <= 80 * 1024}
+    if overflow:
+        raise RuntimeError(f"{src}: kernels overflow 256 vector registers: {sorted(overflow)}")
     with open(obj + ".usage.json", "w") as f:
         json.dump(usage, f, indent=1, sort_keys=True)
     return obj

@@ -244,6 +244,56 @@ bool permutation_of(const PGate& g, int* pi) {
     return true;
 }
 
+// Thread-bit order of a stage: thread bit j <-> local tile bit tb[j], the
+// complement of the stage's register bits.  Correctness does not depend on
+// the order; LDS bank conflicts do.  An LDS access serves the lanes of a
+// wave in groups, and the swizzle (tile_swz) sends local bit b of the
+// (half-)tile index to bank field bit b mod F (F = 4 for 16-byte, 5 for
+// 8-byte amplitudes).  So lanes 0..F-1 should take bits of distinct
+// residues, the lower lanes the residues below F - 1 (groups of 8 lanes are
+// then conflict-free as well as groups of 2^F), both for the reads into the
+// stage (index without the bit hprev) and the writes out of it (without
+// hnext).  Greedy, lane by lane; the first `fixed` lanes keep the ascending
+// order (the coalesced runs of a global load or store), lanes from F on stay
+// ascending.  Returns the number of thread bits.
+int stage_thread_bits(const Stage& st, int k, int hprev, int hnext, int fixed, int elem_bytes,
+                      int* tb) {
+    const int F = elem_bytes == 16 ? 4 : 5;
+    uint32_t used = 0;
+    for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
+    int cand[32], nc = 0;
+    for (int b = 0; b < k; ++b)
+        if (!((used >> b) & 1)) cand[nc++] = b;
+    auto res = [F](int b, int h) { return (h >= 0 && b > h ? b - 1 : b) % F; };
+    bool taken[32] = {};
+    uint32_t seen_r = 0, seen_w = 0;
+    for (int j = 0; j < nc; ++j) {
+        int pick = -1;
+        if (j < fixed || j >= F) {
+            for (int c = 0; c < nc && pick < 0; ++c)
+                if (!taken[c]) pick = c;
+        } else {
+            int best = -1;
+            for (int c = 0; c < nc; ++c) {
+                if (taken[c]) continue;
+                const int rr = res(cand[c], hprev), rw = res(cand[c], hnext);
+                const bool ok_r = !((seen_r >> rr) & 1) && (j == F - 1 || rr != F - 1);
+                const bool ok_w = !((seen_w >> rw) & 1) && (j == F - 1 || rw != F - 1);
+                const int score = int(ok_r) + int(ok_w);
+                if (score > best) {
+                    best = score;
+                    pick = c;
+                }
+            }
+        }
+        taken[pick] = true;
+        tb[j] = cand[pick];
+        seen_r |= 1u << res(cand[pick], hprev);
+        seen_w |= 1u << res(cand[pick], hnext);
+    }
+    return nc;
+}
+
 // Fill the device record of a tile pass at h.  False on a planner bug.
 template <typename R>
 bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
@@ -318,14 +368,23 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
             }
         }
     }
-    // load mapping = first stage's, store mapping = last stage's: thread bits
-    // are the complement of the register bits, ascending
-    auto mapping = [&](const Stage& st, const int* perm, int32_t* tpos, uint64_t* du) {
-        uint32_t used = 0;
-        for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
+    // thread-bit order of every stage; the load mapping is the first
+    // stage's, the store mapping the last stage's
+    std::vector<std::array<int, 32>> tord(static_cast<size_t>(ns));
+    for (int si = 0; si < ns; ++si) {
+        const Stage& st = ps.stages[size_t(si)];
+        const int hprev = ps.split ? st.hprev : -1;
+        const int hnext = (ps.split && si + 1 < ns) ? ps.stages[size_t(si) + 1].hprev : -1;
+        const int fixed = (si == 0 || si == ns - 1) ? ps.coal : 0;
+        if (stage_thread_bits(st, ps.k, hprev, hnext, fixed, int(sizeof(V)), tord[size_t(si)].data()) !=
+            ps.k - st.nr)
+            return false;
+    }
+    auto mapping = [&](int si, const int* perm, int32_t* tpos, uint64_t* du) {
+        const Stage& st = ps.stages[size_t(si)];
+        const int nt = ps.k - st.nr;
         int tj = 0;
-        for (int b = 0; b < ps.k && tj < 10; ++b)
-            if (!((used >> b) & 1)) tpos[tj++] = ps.pos[b];
+        for (; tj < nt && tj < 10; ++tj) tpos[tj] = ps.pos[tord[size_t(si)][size_t(tj)]];
         for (; tj < 10; ++tj) tpos[tj] = 0;
         for (int u = 0; u < 32; ++u) {
             uint64_t off = 0;
@@ -339,19 +398,16 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
     };
     static const int ident[32] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15,
                                   16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
-    mapping(ps.stages.front(), ident, hd->tpos_ld, hd->du);
-    mapping(ps.stages.back(), dest[size_t(ns - 1)].data(), hd->tpos_st, hd->du_st);
+    mapping(0, ident, hd->tpos_ld, hd->du);
+    mapping(ns - 1, dest[size_t(ns - 1)].data(), hd->tpos_st, hd->du_st);
     TStage* ts = reinterpret_cast<TStage*>(h + sizeof(TPassHdr));
     TGate<R>* tg = reinterpret_cast<TGate<R>*>(h + sizeof(TPassHdr) + ps.stages.size() * sizeof(TStage));
     int gi = 0;
     for (int si = 0; si < ns; ++si) {
         const Stage& st = ps.stages[size_t(si)];
         ts[si].gbeg = gi;
-        uint32_t used = 0;
-        for (int j = 0; j < st.nr; ++j) used |= 1u << st.rbits[j];
         int tj = 0;
-        for (int b = 0; b < ps.k && tj < 10; ++b)
-            if (!((used >> b) & 1)) ts[si].tbits[tj++] = b;
+        for (; tj < ps.k - st.nr && tj < 10; ++tj) ts[si].tbits[tj] = tord[size_t(si)][size_t(tj)];
         for (; tj < 10; ++tj) ts[si].tbits[tj] = 0;
         // split exchange: half-tile addresses without the shared bit
         const int hprev = ps.split ? st.hprev : -1;

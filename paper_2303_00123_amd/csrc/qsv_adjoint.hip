@@ -35,15 +35,16 @@ __global__ __launch_bounds__(kThreads) void k_apply_obs(const typename V2T<R>::t
                                                         const uint64_t* __restrict__ masks,
                                                         const double* __restrict__ w) {
     using V = typename V2T<R>::type;
-    const uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (x >= N) return;
-    double d = 0.0;
-    for (int t = 0; t < nt; ++t) d += (__popcll(x & masks[t]) & 1) ? -w[t] : w[t];
-    const V v = psi[x];
-    V o;
-    o.x = R(d * double(v.x));
-    o.y = R(d * double(v.y));
-    lam[x] = o;
+    for (uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x; x < N;
+         x += uint64_t(gridDim.x) * kThreads) {
+        double d = 0.0;
+        for (int t = 0; t < nt; ++t) d += (__popcll(x & masks[t]) & 1) ? -w[t] : w[t];
+        const V v = psi[x];
+        V o;
+        o.x = R(d * double(v.x));
+        o.y = R(d * double(v.y));
+        lam[x] = o;
+    }
 }
 
 // One rotation about `axis` on position p: partial Im<lam|P|psi> over this
@@ -387,7 +388,7 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
     const uint64_t N = uint64_t(1) << n;
     const size_t ng = fwd.size();
     constexpr int KA = AdjShape<R>::K;
-    if (n < KA) fused = false;
+    if (n < KA || n - KA > kMaxTileGridLog2) fused = false;   // too small, or too many tiles for one launch
 
     // observable upload: masks then weights
     const size_t obytes = size_t(nterms) * (sizeof(uint64_t) + sizeof(double));
@@ -404,7 +405,7 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
     const double* dw = reinterpret_cast<const double*>(static_cast<char*>(dev) +
                                                        size_t(nterms) * sizeof(uint64_t));
     prof_before(ctx, sizeof(R) == 8 ? "adj_obs_c128" : "adj_obs_c64", 2.0 * double(N) * sizeof(V));
-    hipLaunchKernelGGL(k_apply_obs<R>, dim3(unsigned((N + kThreads - 1) / kThreads)), dim3(kThreads),
+    hipLaunchKernelGGL(k_apply_obs<R>, dim3(capped_grid((N + kThreads - 1) / kThreads)), dim3(kThreads),
                        0, ctx->stream, static_cast<const V*>(psi), static_cast<V*>(lam), N, nterms,
                        dmask, dw);
     prof_after(ctx);

@@ -205,7 +205,15 @@ __global__ void k_zero(unsigned* __restrict__ p, size_t n) {
 inline int pos_in(int n, int q) { return n - 1 - q; }
 
 struct BatchBuild {
-    std::vector<char> plan;
+    // pass records are written later, straight into the upload buffer
+    // (write_batch_records): per circuit its lowered gates and pass list
+    // (an entry of the plan memo, or `own`), and per pass its record offset
+    int dtype = 0;
+    size_t plan_bytes = 0;
+    std::vector<std::vector<PGate>> lowered;
+    std::vector<std::vector<Pass>> own;
+    std::vector<std::vector<Pass>*> plans;
+    std::vector<size_t> rec_first;   // per circuit: index of its first pass in `passes`
     std::vector<BCirc> circs;
     std::vector<BPass> passes;
     std::vector<BItem> items;
@@ -275,12 +283,16 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
                         const uint64_t* qmasks, const double* w, int dtype, int K, int L,
                         BatchBuild& B, std::vector<PlanMemo>* memo) {
     const size_t amp = amp_bytes(dtype);
+    B.dtype = dtype;
     // per-circuit pass lists: entries of the memo when there is one (reused
     // in place; the one-gate stage fix-up below is idempotent), else local
-    std::vector<std::vector<Pass>> own(static_cast<size_t>(memo ? 0 : nb));
-    std::vector<std::vector<Pass>*> plans(static_cast<size_t>(nb), nullptr);
+    std::vector<std::vector<Pass>>& own = B.own;
+    std::vector<std::vector<Pass>*>& plans = B.plans;
+    own.assign(static_cast<size_t>(memo ? 0 : nb), {});
+    plans.assign(static_cast<size_t>(nb), nullptr);
     if (memo && memo->size() < size_t(nb)) memo->resize(size_t(nb));
-    std::vector<std::vector<PGate>> lowered(static_cast<size_t>(nb));
+    std::vector<std::vector<PGate>>& lowered = B.lowered;
+    lowered.assign(static_cast<size_t>(nb), {});
     mix(B.shape_key, uint64_t(nb));
     mix(B.shape_key, uint64_t(dtype));
     // per circuit, in parallel: lower, fuse, plan (structure hash per circuit)
@@ -377,8 +389,9 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
         B.circs.push_back(bc);
         if (bc.npasses > maxp) maxp = bc.npasses;
     }
-    // pass records: offsets in order, then written in parallel
-    std::vector<size_t> rec_first(static_cast<size_t>(nb) + 1, 0);
+    // pass records: offsets in order (written later by write_batch_records)
+    std::vector<size_t>& rec_first = B.rec_first;
+    rec_first.assign(static_cast<size_t>(nb) + 1, 0);
     {
         size_t total = 0;
         for (int c = 0; c < nb; ++c) {
@@ -396,19 +409,8 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
         }
         rec_first[size_t(nb)] = B.passes.size();
         if (total >= (size_t(1) << 32)) return "batch plan too large";
-        B.plan.assign(total, 0);
+        B.plan_bytes = total;
     }
-    std::atomic<bool> bad{false};
-    const bool written = parallel_for(nb, [&](int c) {
-        const std::vector<Pass>& pl = *plans[size_t(c)];
-        for (size_t p = 0; p < pl.size(); ++p) {
-            const size_t off = B.passes[rec_first[size_t(c)] + p].rec_off;
-            if (!write_pass_record(dtype, B.plan.data() + off, lowered[size_t(c)], pl[p])) bad = true;
-        }
-    });
-    if (!written) return "out of host memory while writing records";
-    if (bad) return "internal planner error";
-    if (B.plan.size() >= (size_t(1) << 32)) return "batch plan too large";
     // items, pass-level-major; within a level, larger circuits first
     std::vector<int> pass_first(static_cast<size_t>(nb), 0);
     {
@@ -433,6 +435,26 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
     return "";
 }
 
+// The pass records of a built batch, written in parallel at dst (plan_bytes
+// bytes; each record is cleared first, so padding is deterministic).
+std::string write_batch_records(const BatchBuild& B, char* dst) {
+    const int nb = int(B.plans.size());
+    std::atomic<bool> bad{false};
+    const bool written = parallel_for(nb, [&](int c) {
+        const std::vector<Pass>& pl = *B.plans[size_t(c)];
+        for (size_t p = 0; p < pl.size(); ++p) {
+            const size_t i = B.rec_first[size_t(c)] + p;
+            const size_t off = B.passes[i].rec_off;
+            const size_t end = i + 1 < B.passes.size() ? B.passes[i + 1].rec_off : B.plan_bytes;
+            std::memset(dst + off, 0, end - off);
+            if (!write_pass_record(B.dtype, dst + off, B.lowered[size_t(c)], pl[p])) bad = true;
+        }
+    });
+    if (!written) return "out of host memory while writing records";
+    if (bad) return "internal planner error";
+    return "";
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
@@ -442,7 +464,7 @@ struct Layout {
 Layout upload_layout(const BatchBuild& B) {
     Layout L{};
     size_t o = 0;
-    L.plan = o; o = align256(o + B.plan.size());
+    L.plan = o; o = align256(o + B.plan_bytes);
     L.circs = o; o = align256(o + B.circs.size() * sizeof(BCirc));
     L.passes = o; o = align256(o + B.passes.size() * sizeof(BPass));
     L.items = o; o = align256(o + B.items.size() * sizeof(BItem));
@@ -607,7 +629,11 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     ctx->batch_part_off = part_off;
     ctx->batch_state_off = state_off;
     char* h = static_cast<char*>(ctx->h_batch);
-    std::memcpy(h + R.L.plan, B.plan.data(), B.plan.size());
+    err = write_batch_records(B, h + R.L.plan);
+    if (!err.empty()) {
+        ctx->last_error = "qsv_batch_run: " + err;
+        return err == "internal planner error" ? QSV_ERR_INTERNAL : QSV_ERR_NOMEM;
+    }
     std::memcpy(h + R.L.circs, B.circs.data(), B.circs.size() * sizeof(BCirc));
     std::memcpy(h + R.L.passes, B.passes.data(), B.passes.size() * sizeof(BPass));
     std::memcpy(h + R.L.items, B.items.data(), B.items.size() * sizeof(BItem));

@@ -14,6 +14,14 @@ struct V2T<double> { using type = double2; };
 template <>
 struct V2T<float> { using type = float2; };
 
+// A dispatch covers at most 2^32 - 1 work-items (grid x block), so kernels
+// whose natural grid could exceed that at 32+ qubits loop over blocks
+// (grid-stride) with their grid capped here: 2^22 blocks of 256 threads.
+constexpr uint64_t kMaxGridBlocks = uint64_t(1) << 22;
+inline unsigned capped_grid(uint64_t blocks) {
+    return unsigned(blocks < 1 ? 1 : (blocks > kMaxGridBlocks ? kMaxGridBlocks : blocks));
+}
+
 template <typename R>
 struct M2 { R v[8]; };   // 2x2 row-major (re, im)
 template <typename R>

@@ -38,15 +38,18 @@ __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* 
                                                          uint64_t N, uint64_t b) {
     using V = typename V2T<R>::type;
     constexpr int P = PPT<R>::value;
-    const uint64_t i0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
+    constexpr uint64_t BS = uint64_t(kThreads) * P;
+    for (uint64_t blk = blockIdx.x; blk * BS < N; blk += gridDim.x) {
+        const uint64_t i0 = blk * BS + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t i = i0 + uint64_t(k) * kThreads;
-        if (i < N) {
-            V v;
-            v.x = (i == b) ? R(1) : R(0);
-            v.y = R(0);
-            s[i] = v;
+        for (int k = 0; k < P; ++k) {
+            const uint64_t i = i0 + uint64_t(k) * kThreads;
+            if (i < N) {
+                V v;
+                v.x = (i == b) ? R(1) : R(0);
+                v.y = R(0);
+                s[i] = v;
+            }
         }
     }
 }
@@ -58,27 +61,30 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
                                                       uint64_t npairs, int p, M2<R> u) {
     using V = typename V2T<R>::type;
     constexpr int P = GatePairs<R>::value;
-    const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
-    const uint64_t w = uint64_t(1) << p;
-    V a[P], b[P];
+    constexpr uint64_t BS = uint64_t(kThreads) * P;
+    for (uint64_t blk = blockIdx.x; blk * BS < npairs; blk += gridDim.x) {
+        const uint64_t j0 = blk * BS + threadIdx.x;
+        const uint64_t w = uint64_t(1) << p;
+        V a[P], b[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < npairs) {
-            const uint64_t ia = insert0(j, p);
-            a[k] = ld_nt(s + ia);
-            b[k] = ld_nt(s + ia + w);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < npairs) {
+                const uint64_t ia = insert0(j, p);
+                a[k] = ld_nt(s + ia);
+                b[k] = ld_nt(s + ia + w);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < npairs) {
-            const uint64_t ia = insert0(j, p);
-            V oa, ob;
-            mv2(u.v, a[k], b[k], oa, ob);
-            st_nt(s + ia, oa);
-            st_nt(s + ia + w, ob);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < npairs) {
+                const uint64_t ia = insert0(j, p);
+                V oa, ob;
+                mv2(u.v, a[k], b[k], oa, ob);
+                st_nt(s + ia, oa);
+                st_nt(s + ia + w, ob);
+            }
         }
     }
 }
@@ -92,28 +98,31 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
                                                        int pt, int cs, M2<R> u) {
     using V = typename V2T<R>::type;
     constexpr int P = GatePairs<R>::value;
-    const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
-    const uint64_t wt = uint64_t(1) << pt;
-    const uint64_t wc = cs ? (uint64_t(1) << pc) : 0;
-    V a[P], b[P];
+    constexpr uint64_t BS = uint64_t(kThreads) * P;
+    for (uint64_t blk = blockIdx.x; blk * BS < npairs; blk += gridDim.x) {
+        const uint64_t j0 = blk * BS + threadIdx.x;
+        const uint64_t wt = uint64_t(1) << pt;
+        const uint64_t wc = cs ? (uint64_t(1) << pc) : 0;
+        V a[P], b[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < npairs) {
-            const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
-            a[k] = ld_nt(s + ia);
-            b[k] = ld_nt(s + ia + wt);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < npairs) {
+                const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
+                a[k] = ld_nt(s + ia);
+                b[k] = ld_nt(s + ia + wt);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < npairs) {
-            const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
-            V oa, ob;
-            mv2(u.v, a[k], b[k], oa, ob);
-            st_nt(s + ia, oa);
-            st_nt(s + ia + wt, ob);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < npairs) {
+                const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
+                V oa, ob;
+                mv2(u.v, a[k], b[k], oa, ob);
+                st_nt(s + ia, oa);
+                st_nt(s + ia + wt, ob);
+            }
         }
     }
 }
@@ -127,31 +136,34 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
                                                       int pb, M4<R> u) {
     using V = typename V2T<R>::type;
     constexpr int P = GateQuads<R>::value;
-    const uint64_t j0 = uint64_t(blockIdx.x) * (kThreads * P) + threadIdx.x;
-    const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
-    V v[P][4];
+    constexpr uint64_t BS = uint64_t(kThreads) * P;
+    for (uint64_t blk = blockIdx.x; blk * BS < nquads; blk += gridDim.x) {
+        const uint64_t j0 = blk * BS + threadIdx.x;
+        const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
+        V v[P][4];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < nquads) {
-            const uint64_t i0 = insert0(insert0(j, plo), phi);
-            v[k][0] = ld_nt(s + i0);
-            v[k][1] = ld_nt(s + i0 + wb);
-            v[k][2] = ld_nt(s + i0 + wa);
-            v[k][3] = ld_nt(s + i0 + wa + wb);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < nquads) {
+                const uint64_t i0 = insert0(insert0(j, plo), phi);
+                v[k][0] = ld_nt(s + i0);
+                v[k][1] = ld_nt(s + i0 + wb);
+                v[k][2] = ld_nt(s + i0 + wa);
+                v[k][3] = ld_nt(s + i0 + wa + wb);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const uint64_t j = j0 + uint64_t(k) * kThreads;
-        if (j < nquads) {
-            const uint64_t i0 = insert0(insert0(j, plo), phi);
-            V o[4];
-            mv4(u.v, v[k], o);
-            st_nt(s + i0, o[0]);
-            st_nt(s + i0 + wb, o[1]);
-            st_nt(s + i0 + wa, o[2]);
-            st_nt(s + i0 + wa + wb, o[3]);
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < nquads) {
+                const uint64_t i0 = insert0(insert0(j, plo), phi);
+                V o[4];
+                mv4(u.v, v[k], o);
+                st_nt(s + i0, o[0]);
+                st_nt(s + i0 + wb, o[1]);
+                st_nt(s + i0 + wa, o[2]);
+                st_nt(s + i0 + wa + wb, o[3]);
+            }
         }
     }
 }
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
 template <typename R>
 unsigned grid_for(uint64_t items, int per_thread) {
     const uint64_t per_block = uint64_t(kThreads) * per_thread;
-    return unsigned((items + per_block - 1) / per_block);
+    return capped_grid((items + per_block - 1) / per_block);
 }
 
 template <typename R>

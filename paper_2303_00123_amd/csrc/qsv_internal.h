@@ -14,6 +14,8 @@
 namespace qsv {
 
 constexpr int kMaxQubits = 36;
+constexpr int kMaxTileBits = 13;       // largest compiled tile (2^13 amplitudes)
+constexpr int kMaxTileGridLog2 = 23;   // tiles per launch (256 threads each, < 2^32 work-items)
 
 inline size_t amp_bytes(int dtype) { return dtype == QSV_C128 ? 16 : 8; }
 

@@ -459,7 +459,9 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
         }
         return passes;
     }
-    const int K = std::min(cfg.tile_bits, n);
+    // a launch covers at most 2^32 - 1 work-items: 2^(n - K) tiles of 256
+    // threads need n - K <= 23, so very large states take larger tiles
+    const int K = std::max(std::min(cfg.tile_bits, n), std::min(n - kMaxTileGridLog2, kMaxTileBits));
     const int L = std::min(cfg.low_bits, K);
     std::vector<int> rem(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);

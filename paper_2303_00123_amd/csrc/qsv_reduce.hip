@@ -128,17 +128,18 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_collapse(typename V2T<R>::type* __restrict__ s,
                                                        uint64_t N, int p, int keep, R scale) {
     using V = typename V2T<R>::type;
-    const uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (x >= N) return;
-    V v = s[x];
-    if (int((x >> p) & 1) == keep) {
-        v.x *= scale;
-        v.y *= scale;
-    } else {
-        v.x = R(0);
-        v.y = R(0);
+    for (uint64_t x = uint64_t(blockIdx.x) * kThreads + threadIdx.x; x < N;
+         x += uint64_t(gridDim.x) * kThreads) {
+        V v = s[x];
+        if (int((x >> p) & 1) == keep) {
+            v.x *= scale;
+            v.y *= scale;
+        } else {
+            v.x = R(0);
+            v.y = R(0);
+        }
+        s[x] = v;
     }
-    s[x] = v;
 }
 
 // Copy nt stage-2 results to the pinned host buffer and wait.
@@ -225,7 +226,7 @@ template <typename R>
 hipError_t collapse_t(qsv_ctx ctx, void* s, int n, int p, int keep, double scale) {
     using V = typename V2T<R>::type;
     const uint64_t N = uint64_t(1) << n;
-    const unsigned G = unsigned((N + kThreads - 1) / kThreads);
+    const unsigned G = capped_grid((N + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_collapse<R>, dim3(G), dim3(kThreads), 0, ctx->stream, static_cast<V*>(s),
                        N, p, keep, R(scale));
     return hipGetLastError();

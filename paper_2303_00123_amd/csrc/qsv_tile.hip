@@ -454,7 +454,8 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
     std::vector<size_t> offs(passes.size(), 0);
     for (size_t i = 0; i < passes.size(); ++i) {
         if (passes[i].single) continue;
-        if (passes[i].k < kMinTileBits || passes[i].k > TileK<R>::value || n - passes[i].k > 30)
+        if (passes[i].k < kMinTileBits || passes[i].k > TileK<R>::value ||
+            n - passes[i].k > kMaxTileGridLog2)
             return hipErrorInvalidValue;
         offs[i] = bytes;
         bytes += record_bytes_t<R>(passes[i]);

@@ -139,6 +139,17 @@ def test_planner_below_min_tile_runs_gate_by_gate():
         q.plan_circuit(14, c.gates, q.QSV_C128, 9, 0)
 
 
+def test_planner_bounds_tiles_per_launch_on_large_states():
+    # a launch covers under 2^32 work-items: 2^(n - K) tiles of 256 threads
+    # need n - K <= 23, so a 34-qubit state takes 2^11-amplitude tiles even
+    # when 2^10 is asked for, and the default 2^13 stays as it is
+    c = W.layered_cnot_brick(34, 1, seed=7)
+    for tb, want in ((10, 11), (0, 13)):
+        pog, order, pq = q.plan_circuit(34, c.gates, q.QSV_C128, tb, 0)
+        ks = {bin(int(m)).count("1") for m in pq}
+        assert ks == {want}, (tb, ks)
+
+
 # ------------------------------------------------------------ fused sequence
 def _records_to_circuit(n, recs):
     """qsv_gate records (explicit matrices) -> a workloads circuit."""

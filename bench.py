@@ -141,33 +141,44 @@ def measured_traffic(n: int):
 
 
 def unfused_sweep(q, W, n: int):
-    """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3)."""
+    """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3).
+
+    A controlled gate moves half the state (2^n * 16 bytes, its algorithmic
+    bytes) when its control is an index bit at or above 3; below that the
+    amplitudes it skips share 128-byte lines with the ones it moves, so HBM
+    carries the whole state.  The sweep keeps controls at bits >= 3 and times
+    the low-control case on its own, reported against both byte counts."""
     import numpy as np
     import torch
     rng = np.random.default_rng(3003)
     gates = []
     for qb in range(n):
         gates.append(W.g1(qb, W.haar_unitary(2, rng)))
-    for qb in range(0, n - 1, 3):
+    for qb in range(0, n - 4, 3):      # control qubit qb: index bit n-1-qb >= 3
         gates.append(W.gc(qb, qb + 1, W.haar_unitary(2, rng)))
+    for qb in range(0, n - 1, 3):
         gates.append(W.g2(qb, n - 1 - qb if n - 1 - qb != qb else qb + 1, W.haar_unitary(4, rng)))
-    g = q.marshal_gates(gates)
+    low = [W.gc(n - 1, 0, W.haar_unitary(2, rng)) for _ in range(4)]   # control at index bit 0
     ctx = q.Context()
     st = q.State(ctx, n, q.QSV_C128)
     st.init_basis(0)
-    st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
-    torch.cuda.synchronize()
-    ctx.profile_begin()
-    st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
-    prof = ctx.profile_end()
+    out = {}
+    for gl, tag in ((gates, ""), (low, "_ctrl_bit0")):
+        g = q.marshal_gates(gl)
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        prof = ctx.profile_end()
+        for k, v in prof.items():
+            out[k + tag] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                            "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
+            if tag:
+                out[k + tag]["GB/s_hbm"] = round(2 * v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)
     st.free()
     del st
     ctx.close()
     torch.cuda.empty_cache()
-    out = {}
-    for k, v in prof.items():
-        out[k] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
-                  "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
     return out
 
 

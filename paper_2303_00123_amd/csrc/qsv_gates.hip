@@ -56,9 +56,15 @@ __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* 
 
 // ------------------------------------------------------------- Alg. 1
 // Pair j -> a_j = insert0(j, p), b_j = a_j + 2^p; 2x2 matvec in place.
-template <typename R>
+// CTRL: Alg. 2 with its control at a low index bit pc (below the 128-byte
+// line): every pair over the target is read and written, and U applies
+// where bit pc of a_j equals cs.  The pairs Alg. 2 would skip share lines
+// with the ones it moves, so HBM carries the whole state either way; this
+// form keeps every access a full, contiguous line.
+template <typename R, bool CTRL = false>
 __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __restrict__ s,
-                                                      uint64_t npairs, int p, M2<R> u) {
+                                                      uint64_t npairs, int p, M2<R> u, int pc = 0,
+                                                      int cs = 0) {
     using V = typename V2T<R>::type;
     constexpr int P = GatePairs<R>::value;
     constexpr uint64_t BS = uint64_t(kThreads) * P;
@@ -82,6 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
                 const uint64_t ia = insert0(j, p);
                 V oa, ob;
                 mv2(u.v, a[k], b[k], oa, ob);
+                if (CTRL && int((ia >> pc) & 1) != cs) {
+                    oa = a[k];
+                    ob = b[k];
+                }
                 st_nt(s + ia, oa);
                 st_nt(s + ia + w, ob);
             }
@@ -204,8 +214,8 @@ hipError_t apply1q_t(qsv_ctx ctx, void* s, int n, int p, const double* u) {
     const uint64_t np = uint64_t(1) << (n - 1);
     prof_before(ctx, sizeof(R) == 8 ? "apply1q_c128" : "apply1q_c64",
                 2.0 * double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL(k_apply1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
-                       ctx->stream, static_cast<V*>(s), np, p, to_m2<R>(u));
+    hipLaunchKernelGGL((k_apply1q<R, false>), dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
+                       ctx->stream, static_cast<V*>(s), np, p, to_m2<R>(u), 0, 0);
     prof_after(ctx);
     return hipGetLastError();
 }
@@ -217,8 +227,16 @@ hipError_t applyc1q_t(qsv_ctx ctx, void* s, int n, int pc, int pt, int cs, const
     const int plo = pc < pt ? pc : pt, phi = pc < pt ? pt : pc;
     prof_before(ctx, sizeof(R) == 8 ? "applyc1q_c128" : "applyc1q_c64",
                 double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL(k_applyc1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
-                       ctx->stream, static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
+    // a control below the 128-byte line: the whole state moves anyway, so
+    // move it in full lines (see k_apply1q)
+    const int line_bits = sizeof(R) == 8 ? 3 : 4;
+    if (pc < line_bits)
+        hipLaunchKernelGGL((k_apply1q<R, true>), dim3(grid_for<R>(2 * np, GatePairs<R>::value)),
+                           dim3(kThreads), 0, ctx->stream, static_cast<V*>(s), 2 * np, pt,
+                           to_m2<R>(u), pc, cs);
+    else
+        hipLaunchKernelGGL(k_applyc1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
+                           ctx->stream, static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
     prof_after(ctx);
     return hipGetLastError();
 }

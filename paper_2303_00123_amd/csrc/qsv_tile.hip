@@ -175,9 +175,7 @@ hipError_t launch_tile(qsv_ctx ctx, void* s, int n, bool split, const char* dpla
     return hipGetLastError();
 }
 
-// The compiled (tile bits, register bits) shapes: 256 threads for every
-// tile size, plus 512-thread variants (more waves per SIMD) at 2^12 and 2^13
-// and 2^13-amplitude tiles with 32 amplitudes per thread.
+// The compiled (tile bits, register bits) shapes, 256 threads each.
 template <typename R>
 hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, bool split, const char* dplan) {
     switch (k * 8 + rb) {

@@ -173,14 +173,15 @@ __device__ __forceinline__ void apply_gate2(V (&v)[P], V (&l)[P], const TGate<R>
             }
         });
         part = wave_sum_to_lane63(part);
-        if ((tid & 63) == 63) part_out[size_t(g.r1) * 4 + (tid >> 6)] = part;
+        if ((tid & 63) == 63) part_out[size_t(g.r1) * gridDim.x * 4 + (tid >> 6)] = part;
     } else {
         apply_op2_inplace<RB>(v, l, g.kind * 64 + g.r0 * 8 + g.r1, g.m);
     }
 }
 
 // One two-vector tile pass.  partials: this pass's block of
-// [tile][slot][wave] doubles (slot count in the header's pad field).
+// [slot][tile][wave] doubles (slot count in the header's pad field), so the
+// per-rotation sums read each slot's row contiguously.
 // SPLIT: consecutive stages share a register bit and each vector changes
 // mapping in two half-tile rounds through LDS (see run_stages), so the two
 // tiles take half the LDS.
@@ -202,11 +203,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     const TPassHdr* hdr = reinterpret_cast<const TPassHdr*>(plan);
     const TStage* stg = reinterpret_cast<const TStage*>(plan + sizeof(TPassHdr));
     const int nst = hdr->nstages;
-    const int nslot = hdr->pad;
     const TGate<R>* gates = reinterpret_cast<const TGate<R>*>(plan + sizeof(TPassHdr) +
                                                               size_t(nst) * sizeof(TStage));
     const uint32_t tid = threadIdx.x;
-    double* const part_out = partials + size_t(blockIdx.x) * size_t(nslot) * 4;
+    double* const part_out = partials + size_t(blockIdx.x) * 4;
 
     uint64_t b = blockIdx.x;
 #pragma unroll
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(typename V2T<R>::type* __
     }
 }
 
-// grad[tag[s]] = sum over (tile, wave) of partials[(tile * nslot + s) * 4 + wave], fixed order
+// grad[tag[s]] = sum over (tile, wave) of partials[(s * tiles + tile) * 4 + wave], fixed order
 __global__ __launch_bounds__(kThreads) void k_adj_cols(const double* __restrict__ partials,
                                                        int tiles, int nslot,
                                                        const int32_t* __restrict__ tags,
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_cols(const double* __restrict_
     const int s = blockIdx.x;
     double acc = 0.0;
     for (int t = threadIdx.x; t < tiles; t += kThreads) {
-        const double* p = partials + (size_t(t) * nslot + s) * 4;
+        const double* p = partials + (size_t(s) * tiles + t) * 4;
         acc += (p[0] + p[1]) + (p[2] + p[3]);
     }
     red[0][threadIdx.x] = acc;

@@ -140,25 +140,26 @@ def measured_traffic(n: int):
     return rec.get("traffic_bytes_per_launch")
 
 
-def unfused_sweep(q, W, n: int):
+def unfused_sweep(q, W, n: int, every: int = 1):
     """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3).
 
     A controlled gate moves half the state (2^n * 16 bytes, its algorithmic
     bytes) when its control is an index bit at or above 3; below that the
     amplitudes it skips share 128-byte lines with the ones it moves, so HBM
     carries the whole state.  The sweep keeps controls at bits >= 3 and times
-    the low-control case on its own, reported against both byte counts."""
+    the low-control case on its own, reported against both byte counts.
+    every = k uses every k-th qubit position (a shorter sweep)."""
     import numpy as np
     import torch
     rng = np.random.default_rng(3003)
     gates = []
-    for qb in range(n):
+    for qb in range(0, n, every):
         gates.append(W.g1(qb, W.haar_unitary(2, rng)))
-    for qb in range(0, n - 4, 3):      # control qubit qb: index bit n-1-qb >= 3
+    for qb in range(0, n - 4, 3 * every):      # control qubit qb: index bit n-1-qb >= 3
         gates.append(W.gc(qb, qb + 1, W.haar_unitary(2, rng)))
-    for qb in range(0, n - 1, 3):
+    for qb in range(0, n - 1, 3 * every):
         gates.append(W.g2(qb, n - 1 - qb if n - 1 - qb != qb else qb + 1, W.haar_unitary(4, rng)))
-    low = [W.gc(n - 1, 0, W.haar_unitary(2, rng)) for _ in range(4)]   # control at index bit 0
+    low = [W.gc(n - 1, 0, W.haar_unitary(2, rng)) for _ in range(4 if every == 1 else 2)]   # control at index bit 0
     ctx = q.Context()
     st = q.State(ctx, n, q.QSV_C128)
     st.init_basis(0)
@@ -334,6 +335,9 @@ def main():
                                                      r64["flops_per_step"], "f32")}
         log("extras: unfused sweep")
         extras["unfused_c128"] = unfused_sweep(q, W, args.n)
+        if args.n == 30:
+            log("extras: unfused sweep at 32 qubits")
+            extras["unfused_c128_n32"] = unfused_sweep(q, W, 32, every=4)
         log("extras: adjoint ratio")
         extras["adjoint"] = adjoint_ratio(q, W)
         log("extras: batch")

@@ -437,15 +437,17 @@ hipError_t adjoint_t(qsv_ctx ctx, void* psi, void* lam, int n, const std::vector
             rev.push_back(d);
         }
         rev = prefuse(rev);
-        std::vector<Pass> passes =
-            plan_passes(n, rev, TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt),
-                                         AdjShape<R>::SPLIT ? 1 : 0});
+        // same structure as the last sweep (new angles): same passes
+        const std::vector<Pass>& passes =
+            plan_memo(ctx->adj_memo, n, rev,
+                      TileConfig{KA, sizeof(R) == 8 ? 3 : 4, KA - 8, coal_bits_for(dt),
+                                 AdjShape<R>::SPLIT ? 1 : 0});
         // slots, record layout, partial-buffer size
         size_t bytes = 0, max_part = 0;
         std::vector<size_t> offs(passes.size(), 0), tag_off(passes.size(), 0);
         std::vector<int> nslot(passes.size(), 0);
         for (size_t i = 0; i < passes.size(); ++i) {
-            Pass& ps = passes[i];
+            const Pass& ps = passes[i];
             if (ps.single) continue;
             int s = 0;
             for (int gi : ps.gates)

@@ -515,7 +515,7 @@ static bool same_gates(const std::vector<PGate>& a, const std::vector<PGate>& b)
 
 static bool same_cfg(const TileConfig& a, const TileConfig& b) {
     return a.tile_bits == b.tile_bits && a.low_bits == b.low_bits && a.reg_bits == b.reg_bits &&
-           a.coal_bits == b.coal_bits;
+           a.coal_bits == b.coal_bits && a.split == b.split;
 }
 
 // Fused application of lowered gates on one state.  Fusion, planning and

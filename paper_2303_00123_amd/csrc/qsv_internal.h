@@ -227,6 +227,7 @@ struct qsv_ctx_s {
     qsv::PlanMemo memo;                 // their passes
     bool plan_resident = false;         // d_plan holds the records of memo.passes
     std::vector<qsv::PlanMemo> batch_memo;   // per circuit of the last batch
+    qsv::PlanMemo adj_memo;             // passes of the last adjoint sweep's reversed circuit
 };
 
 struct qsv_state_s {

@@ -505,7 +505,8 @@ const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>&
                  (uint32_t(is_1q(g.kind) ? 0 : (g.p1 & 63)) << 11) | (uint32_t(g.cs & 1) << 17);
     }
     const bool same = m.n == n && m.cfg.tile_bits == cfg.tile_bits && m.cfg.low_bits == cfg.low_bits &&
-                      m.cfg.reg_bits == cfg.reg_bits && m.cfg.coal_bits == cfg.coal_bits && m.sig == sig;
+                      m.cfg.reg_bits == cfg.reg_bits && m.cfg.coal_bits == cfg.coal_bits &&
+                      m.cfg.split == cfg.split && m.sig == sig;
     if (!same) {
         m.passes = plan_passes(n, fused, cfg);
         m.n = n;

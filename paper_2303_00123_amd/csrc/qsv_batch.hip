@@ -437,7 +437,9 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
 
 // The pass records of a built batch, written in parallel at dst (plan_bytes
 // bytes; each record is cleared first, so padding is deterministic).
-std::string write_batch_records(const BatchBuild& B, char* dst) {
+// QSV_ERR_NOMEM if a worker ran out of host memory, QSV_ERR_INTERNAL on a
+// planner inconsistency.
+qsv_status write_batch_records(const BatchBuild& B, char* dst) {
     const int nb = int(B.plans.size());
     std::atomic<bool> bad{false};
     const bool written = parallel_for(nb, [&](int c) {
@@ -450,9 +452,8 @@ std::string write_batch_records(const BatchBuild& B, char* dst) {
             if (!write_pass_record(B.dtype, dst + off, B.lowered[size_t(c)], pl[p])) bad = true;
         }
     });
-    if (!written) return "out of host memory while writing records";
-    if (bad) return "internal planner error";
-    return "";
+    if (!written) return QSV_ERR_NOMEM;
+    return bad ? QSV_ERR_INTERNAL : QSV_OK;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -629,10 +630,10 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     ctx->batch_part_off = part_off;
     ctx->batch_state_off = state_off;
     char* h = static_cast<char*>(ctx->h_batch);
-    err = write_batch_records(B, h + R.L.plan);
-    if (!err.empty()) {
-        ctx->last_error = "qsv_batch_run: " + err;
-        return err == "internal planner error" ? QSV_ERR_INTERNAL : QSV_ERR_NOMEM;
+    if (qsv_status ws = write_batch_records(B, h + R.L.plan)) {
+        ctx->last_error = ws == QSV_ERR_NOMEM ? "qsv_batch_run: out of host memory while writing records"
+                                              : "qsv_batch_run: internal planner error";
+        return ws;
     }
     std::memcpy(h + R.L.circs, B.circs.data(), B.circs.size() * sizeof(BCirc));
     std::memcpy(h + R.L.passes, B.passes.data(), B.passes.size() * sizeof(BPass));

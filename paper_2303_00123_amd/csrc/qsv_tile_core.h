@@ -256,10 +256,6 @@ __device__ __forceinline__ void apply_op2_inplace(V (&v1)[P], V (&v2)[P], int op
     });
 }
 
-template <int RB, typename R, typename V, int P>
-__device__ __forceinline__ void apply_gate(const V (&s)[P], V (&d)[P], const TGate<R>& g) {
-    apply_op<RB>(s, d, g.kind * 64 + g.r0 * 8 + g.r1, g.m);
-}
 #undef QSV_EACH
 #undef QSV_C1ALL
 #undef QSV_C2ALL

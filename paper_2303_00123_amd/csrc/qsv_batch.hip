@@ -748,9 +748,13 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                     s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
                                     sh[0], sh[1], Rc, k2);
                     if (s != QSV_OK) return s;
-                    hipEvent_t e0, e1;
-                    hipEventCreate(&e0);
-                    hipEventCreate(&e1);
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                        if (e0) hipEventDestroy(e0);
+                        (void)hipGetLastError();
+                        ctx->last_error = "qsv_batch_run: could not create the tuner's timing events";
+                        return QSV_ERR_HIP;
+                    }
                     hipEventRecord(e0, ctx->stream);
                     hipError_t e = enqueue_batch(ctx, ctx->stream, dtype, sh[0], nb, Rc);
                     hipEventRecord(e1, ctx->stream);

@@ -266,7 +266,9 @@ qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
  * whole tile goes through LDS at once; 2 = consecutive stages share a
  * register bit and the tile moves in two halves, so a workgroup needs half
  * the LDS and more workgroups fit on a compute unit (0 = 2).
- * States with fewer than 10 qubits run one kernel per gate. */
+ * States with fewer than 10 qubits run one kernel per gate.  A launch covers
+ * fewer than 2^32 work-items, so a state of more than tile_bits + 23 qubits
+ * takes tiles of 2^(n - 23) amplitudes (at most 2^13) regardless. */
 qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits,
                         int lds_rounds);
 

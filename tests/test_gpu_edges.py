@@ -7,7 +7,8 @@
     and store offsets, so every path must reproduce the oracle exactly;
   * the adjoint sweep of a circuit without rotation angles (value only);
   * a batch holding an empty circuit, a one-gate circuit and a circuit
-    without observable terms (whose value is 0).
+    without observable terms (whose value is 0);
+  * a context rebound to another stream, and the state query.
 """
 import numpy as np
 import pytest
@@ -108,3 +109,31 @@ def test_batch_with_empty_and_termless_circuits(q, ctx, dtype):
     assert got[0] == pytest.approx(1.5, abs=1e-15)
     assert got[2] == 0.0
     assert np.max(np.abs(got - ref)) <= (1e-12 if dtype == 2 else 2e-5) * 2
+
+
+def test_context_on_a_torch_stream_and_state_info(q):
+    """A context rebound to a torch stream runs there (results by the oracle);
+    qsv_state_info reports the wrapped buffer."""
+    import ctypes
+    import torch
+    lib = q.qsv.lib()
+    s = torch.cuda.Stream()
+    ctx = q.Context()
+    ctx.set_stream(s.cuda_stream)
+    c = W.random_mix(12, 60, seed=21)
+    for dtype in (q.QSV_C128, q.QSV_C64):
+        st = q.State(ctx, 12, dtype)
+        n, dt, ptr = ctypes.c_int(), ctypes.c_int(), ctypes.c_void_p()
+        assert lib.qsv_state_info(st.handle, ctypes.byref(n), ctypes.byref(dt), ctypes.byref(ptr)) == 0
+        assert (n.value, dt.value, ptr.value) == (12, dtype, st.tensor.data_ptr())
+        st.init_basis(0)
+        st.apply_circuit(c.gates)
+        s.synchronize()
+        got = st.tensor.cpu().numpy().astype(np.complex128)
+        ref = O.run(c)
+        if dtype == q.QSV_C128:
+            assert np.max(np.abs(got - ref)) < 1e-12
+        else:
+            assert 1.0 - abs(np.vdot(got, ref)) ** 2 < 1e-6
+        st.free()
+    ctx.close()

@@ -9,6 +9,8 @@ amplitude:
     the oracle's product of per-qubit amplitudes;
   * complex64 run of the same circuit agrees with complex128 (infidelity).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -144,3 +146,26 @@ def test_config3_32_qubits_c64_vs_c128(q):
             assert abs(complex(a.tensor[0].item()) - 1.0) <= 1e-10
         a.free()
     ctx.close()
+
+
+@pytest.mark.skipif(not os.environ.get("QSV_LONG_TESTS"),
+                    reason="minutes of host time for the oracle; set QSV_LONG_TESTS=1")
+def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
+    """The 28-qubit brick circuit (20 layers, 1140 gates) in the benchmark's
+    launch configuration against the FP64 oracle run on the host over the
+    whole 2^28-amplitude state (8 GiB of host memory, a few minutes)."""
+    c = W.config2()
+    st = q.State(ctx, c.n)
+    st.init_basis(0)
+    st.apply_circuit(c.gates)
+    got = st.to_numpy()
+    st.free()
+    ref = None
+    chunk = 60
+    for k in range(0, len(c.gates), chunk):
+        part = W.Circuit(c.n, c.gates[k:k + chunk])
+        ref = O.run(part, state=ref)
+        print(f"oracle: {min(k + chunk, len(c.gates))}/{len(c.gates)} gates", flush=True)
+    err = float(np.max(np.abs(got - ref)))
+    print(f"28-qubit brick: max |d amp| = {err:.3e}", flush=True)
+    assert err <= 1e-12

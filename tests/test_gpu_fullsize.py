@@ -150,7 +150,8 @@ def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
     """The 28-qubit brick circuit (20 layers, 1100 gates) in the benchmark's
     launch configuration against the FP64 oracle run on the host over the
     whole 2^28-amplitude state (about 16 GiB of host memory and under a
-    minute on 16 cores), amplitude by amplitude."""
+    minute on 16 cores), amplitude by amplitude; the complex64 run against
+    the same state by infidelity."""
     c = W.config2()
     st = q.State(ctx, c.n)
     st.init_basis(0)
@@ -166,3 +167,11 @@ def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
     err = float(np.max(np.abs(got - ref)))
     print(f"28-qubit brick: max |d amp| = {err:.3e}", flush=True)
     assert err <= 1e-12
+    # the complex64 path against the same oracle state: infidelity
+    st = q.State(ctx, c.n, q.QSV_C64)
+    st.init_basis(0)
+    st.apply_circuit(c.gates)
+    inf = 1.0 - abs(np.vdot(st.to_numpy().astype(np.complex128), ref)) ** 2
+    st.free()
+    print(f"28-qubit brick, complex64: infidelity = {inf:.3e}", flush=True)
+    assert inf <= 1e-6

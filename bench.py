@@ -51,8 +51,8 @@ def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20,
     obs = [((), 1.0)] + list(c.observable)
 
     def step():
-        st.init_basis(0)
-        st.apply_circuit(None, marshalled=g)
+        # |0...0>, then the circuit: the first tile pass makes |0...0> itself
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_FROM_ZERO)
         return st.expect_z(obs)
 
     for _ in range(warmup):

@@ -78,7 +78,8 @@ enum {
     QSV_FLAG_NO_FUSE = 1,        /* one kernel per gate (Algs. 1-3 unfused)          */
     QSV_FLAG_FORWARD = 2,        /* qsv_adjoint: run the circuit from |0...0> first  */
     QSV_FLAG_CAPTURE_GRAPH = 4,  /* qsv_batch_run: capture and replay a hipGraph     */
-    QSV_FLAG_TUNE = 8            /* qsv_batch_run: autotune the tile shape            */
+    QSV_FLAG_TUNE = 8,           /* qsv_batch_run: autotune the tile shape            */
+    QSV_FLAG_FROM_ZERO = 16      /* qsv_apply_circuit: start from |0...0>, see there  */
 };
 
 typedef struct qsv_ctx_s* qsv_ctx;
@@ -165,7 +166,11 @@ qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u);
  * default gates are grouped into fused passes: each pass loads a tile of
  * amplitudes over a set of qubits once from HBM, applies every gate of the
  * group to it, and stores it once.  Gates on disjoint qubits are reordered
- * only where they commute.  QSV_FLAG_NO_FUSE applies one kernel per gate. */
+ * only where they commute.  QSV_FLAG_NO_FUSE applies one kernel per gate.
+ * QSV_FLAG_FROM_ZERO: the state is first set to |0...0>, as qsv_init_basis
+ * with b = 0 would, and the result is the circuit applied to that; when the
+ * first pass is a fused one it makes |0...0> in registers instead of reading
+ * the state, which saves one write and one read of it. */
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags);
 

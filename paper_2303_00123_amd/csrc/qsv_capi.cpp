@@ -522,7 +522,8 @@ static bool same_cfg(const TileConfig& a, const TileConfig& b) {
 // the device records are reused while the circuit and the tile shape stay
 // the same (the common case of repeated evaluation), so a repeated call
 // costs one comparison on the host and no upload.
-static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<PGate>&& pg) {
+static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<PGate>&& pg,
+                            bool from_zero = false) {
     const TileConfig& cfg = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
     const bool hit = ctx->cache_n == n && ctx->cache_dtype == dtype && same_cfg(ctx->cache_cfg, cfg) &&
                      same_gates(ctx->cache_in, pg);
@@ -547,7 +548,7 @@ static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<
              n, ctx->cache_in.size(), ctx->cache_pg.size(), ctx->memo.passes.size(), singles, stages,
              cfg.tile_bits, cfg.low_bits, hit ? (ctx->plan_resident ? "reused" : "re-uploaded") : "new");
     }
-    return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->memo.passes, true);
+    return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->memo.passes, true, from_zero);
 }
 
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
@@ -557,16 +558,19 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
         qsv_ctx ctx = st->ctx;
         if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
         if (nparams < 0) return fail(ctx, QSV_ERR_ARG, "negative parameter count");
-        if (flags & ~QSV_FLAG_NO_FUSE) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+        if (flags & ~(QSV_FLAG_NO_FUSE | QSV_FLAG_FROM_ZERO)) return fail(ctx, QSV_ERR_ARG, "unknown flag");
         std::vector<PGate> pg;
         if (qsv_status s = lower(ctx, st->n, g, ng, params, nparams, pg)) return s;
+        const bool from_zero = (flags & QSV_FLAG_FROM_ZERO) != 0;
+        if (from_zero && (pg.empty() || (flags & QSV_FLAG_NO_FUSE)))
+            HIP_OR_FAIL(ctx, launch_init_basis(ctx, st->ptr, st->n, st->dtype, 0), "init");
         if (pg.empty()) return QSV_OK;
         if (flags & QSV_FLAG_NO_FUSE) {
             for (const PGate& x : pg)
                 HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
             return QSV_OK;
         }
-        HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg)), "tile passes");
+        HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg), from_zero), "tile passes");
         return QSV_OK;
     } catch (const std::bad_alloc&) {
         return QSV_ERR_NOMEM;
@@ -750,15 +754,14 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
                 if ((qmasks[t] >> q) & 1) pm[t] |= uint64_t(1) << pos_of(n, q);
         }
         if (flags & QSV_FLAG_FORWARD) {
-            HIP_OR_FAIL(ctx, launch_init_basis(ctx, psi->ptr, n, psi->dtype, 0), "init");
-            if (!fwd.empty()) {
-                if (flags & QSV_FLAG_NO_FUSE) {
-                    for (const PGate& x : fwd)
-                        HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
-                } else {
-                    HIP_OR_FAIL(ctx, run_fused(ctx, psi->ptr, n, psi->dtype, std::vector<PGate>(fwd)),
-                                "forward passes");
-                }
+            if (fwd.empty() || (flags & QSV_FLAG_NO_FUSE)) {
+                HIP_OR_FAIL(ctx, launch_init_basis(ctx, psi->ptr, n, psi->dtype, 0), "init");
+                for (const PGate& x : fwd)
+                    HIP_OR_FAIL(ctx, launch_gate(ctx, psi->ptr, n, psi->dtype, x), "gate launch");
+            } else {
+                // |0...0> made by the first tile pass (or set first, see run_passes)
+                HIP_OR_FAIL(ctx, run_fused(ctx, psi->ptr, n, psi->dtype, std::vector<PGate>(fwd), true),
+                            "forward passes");
             }
         }
         std::vector<double> terms(size_t(nterms), 0.0);

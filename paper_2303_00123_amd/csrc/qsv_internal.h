@@ -293,7 +293,7 @@ const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>&
 // cached: the passes are ctx->memo.passes; their records are uploaded only
 // if d_plan no longer holds them.
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
-                      const std::vector<Pass>& passes, bool cached = false);
+                      const std::vector<Pass>& passes, bool cached = false, bool from_zero = false);
 
 // Reductions.  Stage-1 partials go to ctx scratch; results land in host memory.
 // Z-string sums: out[t] = sum_x |s_x|^2 (-1)^{popcount(x & pmask[t])}, t < nt.

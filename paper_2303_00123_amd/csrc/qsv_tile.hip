@@ -33,7 +33,7 @@ using namespace tile;
 // dispatch is compiled once.  Slot offsets come precomputed in the plan.
 template <typename R, int K, int RB, bool SPLIT>
 __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* __restrict__ s,
-                                                        const char* __restrict__ plan) {
+                                                        const char* __restrict__ plan, int from_zero) {
     using V = typename V2T<R>::type;
     constexpr int E = SPLIT ? 1 << (K - 1) : 1 << K;   // LDS amplitudes
     constexpr int TB = K - RB;
@@ -60,14 +60,25 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_tile(typename V2T<R>::type* _
     // uniform offset du[u] (disjoint bits, so OR == ADD)
 #pragma unroll
     for (int i = 0; i < K; ++i) b = insert0(b, hdr->pos[i]);
-    V* const sp = s + (b | deposit(tid, hdr->tpos_ld, TB));
+    const uint64_t xt = b | deposit(tid, hdr->tpos_ld, TB);
+    V* const sp = s + xt;
 
     // memory and LDS phases run at raised wave priority, so the other
     // resident workgroup's arithmetic fills the gaps instead of delaying them
     V v[P];
     __builtin_amdgcn_s_setprio(2);
+    if (from_zero) {
+        // the circuit starts from |0...0>: the first pass makes it in
+        // registers (amplitude 1 at index 0) instead of reading the state
 #pragma unroll
-    for (int u = 0; u < P; ++u) v[u] = ld_nt(sp + hdr->du[u]);
+        for (int u = 0; u < P; ++u) {
+            v[u].x = (xt | hdr->du[u]) == 0 ? R(1) : R(0);
+            v[u].y = R(0);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < P; ++u) v[u] = ld_nt(sp + hdr->du[u]);
+    }
     __builtin_amdgcn_s_setprio(0);
     run_stages<R, K, RB, SPLIT>(v, lds, stg, nst, gates, tid);
     V* const sq = s + (b | deposit(tid, hdr->tpos_st, TB));
@@ -163,28 +174,29 @@ bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t
 }
 
 template <typename R, int K, int RB>
-hipError_t launch_tile(qsv_ctx ctx, void* s, int n, bool split, const char* dplan) {
+hipError_t launch_tile(qsv_ctx ctx, void* s, int n, bool split, const char* dplan, int from_zero) {
     using V = typename V2T<R>::type;
     const unsigned tiles = unsigned(uint64_t(1) << (n - K));
     if (split)
         hipLaunchKernelGGL((k_tile<R, K, RB, true>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
-                           static_cast<V*>(s), dplan);
+                           static_cast<V*>(s), dplan, from_zero);
     else
         hipLaunchKernelGGL((k_tile<R, K, RB, false>), dim3(tiles), dim3(1 << (K - RB)), 0, ctx->stream,
-                           static_cast<V*>(s), dplan);
+                           static_cast<V*>(s), dplan, from_zero);
     return hipGetLastError();
 }
 
 // The compiled (tile bits, register bits) shapes, 256 threads each.
 template <typename R>
-hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, bool split, const char* dplan) {
+hipError_t launch_tile_k(qsv_ctx ctx, void* s, int n, int k, int rb, bool split, const char* dplan,
+                         int fz) {
     switch (k * 8 + rb) {
-    case 10 * 8 + 2: return launch_tile<R, 10, 2>(ctx, s, n, split, dplan);
-    case 11 * 8 + 3: return launch_tile<R, 11, 3>(ctx, s, n, split, dplan);
-    case 12 * 8 + 3: return launch_tile<R, 12, 3>(ctx, s, n, split, dplan);
-    case 12 * 8 + 4: return launch_tile<R, 12, 4>(ctx, s, n, split, dplan);
-    case 13 * 8 + 4: return launch_tile<R, 13, 4>(ctx, s, n, split, dplan);
-    case 13 * 8 + 5: return launch_tile<R, 13, 5>(ctx, s, n, split, dplan);
+    case 10 * 8 + 2: return launch_tile<R, 10, 2>(ctx, s, n, split, dplan, fz);
+    case 11 * 8 + 3: return launch_tile<R, 11, 3>(ctx, s, n, split, dplan, fz);
+    case 12 * 8 + 3: return launch_tile<R, 12, 3>(ctx, s, n, split, dplan, fz);
+    case 12 * 8 + 4: return launch_tile<R, 12, 4>(ctx, s, n, split, dplan, fz);
+    case 13 * 8 + 4: return launch_tile<R, 13, 4>(ctx, s, n, split, dplan, fz);
+    case 13 * 8 + 5: return launch_tile<R, 13, 5>(ctx, s, n, split, dplan, fz);
     default: return hipErrorInvalidValue;
     }
 }
@@ -445,7 +457,7 @@ bool write_record_t(char* h, const std::vector<PGate>& gates, const Pass& ps) {
 
 template <typename R>
 hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& gates,
-                        const std::vector<Pass>& passes, bool cached) {
+                        const std::vector<Pass>& passes, bool cached, bool from_zero) {
     using V = typename V2T<R>::type;
     // upload layout: one record per tile pass
     size_t bytes = 0;
@@ -477,14 +489,22 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
     }
     const char* pname = sizeof(R) == 8 ? "tile_pass_c128" : "tile_pass_c64";
     const int dt = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
+    // from_zero: the first pass makes |0...0> itself when it is a tile pass;
+    // otherwise the state is set first
+    const bool gen_first = from_zero && !passes.empty() && !passes[0].single;
+    if (from_zero && !gen_first) {
+        hipError_t e = launch_init_basis(ctx, s, n, dt, 0);
+        if (e != hipSuccess) return e;
+    }
     for (size_t i = 0; i < passes.size(); ++i) {
         const Pass& ps = passes[i];
         hipError_t e;
         if (ps.single) {
             e = launch_gate(ctx, s, n, dt, gates[size_t(ps.gates[0])]);
         } else {
-            prof_before(ctx, pname, 2.0 * double(uint64_t(1) << n) * sizeof(V));
-            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, ps.split, dev + offs[i]);
+            const bool gen = gen_first && i == 0;   // writes the state without reading it
+            prof_before(ctx, pname, (gen ? 1.0 : 2.0) * double(uint64_t(1) << n) * sizeof(V));
+            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, ps.split, dev + offs[i], gen ? 1 : 0);
             prof_after(ctx);
         }
         if (e != hipSuccess) return e;
@@ -515,9 +535,9 @@ bool tile_shape_supported(int dtype, int tile_bits, int reg_bits) {
 int tile_bits_max(int dtype) { return dtype == QSV_C128 ? TileK<double>::value : TileK<float>::value; }
 
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
-                      const std::vector<Pass>& passes, bool cached) {
-    return dtype == QSV_C128 ? run_passes_t<double>(ctx, s, n, gates, passes, cached)
-                             : run_passes_t<float>(ctx, s, n, gates, passes, cached);
+                      const std::vector<Pass>& passes, bool cached, bool from_zero) {
+    return dtype == QSV_C128 ? run_passes_t<double>(ctx, s, n, gates, passes, cached, from_zero)
+                             : run_passes_t<float>(ctx, s, n, gates, passes, cached, from_zero);
 }
 
 }  // namespace qsv

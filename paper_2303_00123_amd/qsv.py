@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 QSV_OK = 0
 QSV_C64, QSV_C128 = 1, 2
 G1Q, GC1Q, G2Q, GROT = 0, 1, 2, 3
-FLAG_NO_FUSE, FLAG_FORWARD, FLAG_CAPTURE_GRAPH, FLAG_TUNE = 1, 2, 4, 8
+FLAG_NO_FUSE, FLAG_FORWARD, FLAG_CAPTURE_GRAPH, FLAG_TUNE, FLAG_FROM_ZERO = 1, 2, 4, 8, 16
 AXES = {"X": 0, "Y": 1, "Z": 2}
 KINDS = {"1q": G1Q, "c1q": GC1Q, "2q": G2Q, "rot": GROT}
 

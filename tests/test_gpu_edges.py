@@ -8,7 +8,8 @@
   * the adjoint sweep of a circuit without rotation angles (value only);
   * a batch holding an empty circuit, a one-gate circuit and a circuit
     without observable terms (whose value is 0);
-  * a context rebound to another stream, and the state query.
+  * a context rebound to another stream, and the state query;
+  * the from-|0...0> flag of the circuit call.
 """
 import numpy as np
 import pytest
@@ -137,3 +138,31 @@ def test_context_on_a_torch_stream_and_state_info(q):
             assert 1.0 - abs(np.vdot(got, ref)) ** 2 < 1e-6
         st.free()
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [9, 12, 16])
+def test_from_zero_flag(q, ctx, n):
+    """QSV_FLAG_FROM_ZERO: the result is the circuit applied to |0...0>
+    whatever the state held before (the first fused pass makes |0...0> in
+    registers); also with one kernel per gate, a circuit whose first pass is
+    a single gate, and an empty circuit."""
+    rng = np.random.default_rng(500 + n)
+    c = W.random_mix(n, 40, seed=60 + n)
+    one = [W.g1(n - 1, W.haar_unitary(2, rng))]
+    ref = O.run(c)
+    ref_one = O.run(W.Circuit(n, one))
+    zero = O.basis(n)
+    junk = W.random_state(n, seed=7)
+    for dtype in (q.QSV_C128, q.QSV_C64):
+        cdt = np.complex128 if dtype == q.QSV_C128 else np.complex64
+        st = q.State(ctx, n, dtype)
+        for gates, want in ((c.gates, ref), (one, ref_one), ([], zero)):
+            for flags in (q.FLAG_FROM_ZERO, q.FLAG_FROM_ZERO | q.FLAG_NO_FUSE):
+                st.from_numpy(junk.astype(cdt))
+                st.apply_circuit(gates, flags=flags)
+                got = st.to_numpy().astype(np.complex128)
+                if dtype == q.QSV_C128:
+                    assert np.max(np.abs(got - want)) < 1e-12, (len(gates), flags)
+                else:
+                    assert 1.0 - abs(np.vdot(got, want)) ** 2 < 1e-6, (len(gates), flags)
+        st.free()

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .qsv import FLAG_FORWARD, GROT, QSV_C128, Context, State, adjoint, marshal_gates
+from .qsv import FLAG_FORWARD, FLAG_FROM_ZERO, GROT, QSV_C128, Context, State, adjoint, marshal_gates
 
 __all__ = ["Expectation"]
 
@@ -57,8 +57,7 @@ class Expectation:
 
     def value(self, theta: np.ndarray) -> float:
         p = np.ascontiguousarray(theta, dtype=np.float64)
-        self.psi.init_basis(0)
-        self.psi.apply_circuit(None, p, marshalled=self.g)
+        self.psi.apply_circuit(None, p, flags=FLAG_FROM_ZERO, marshalled=self.g)
         self._version += 1
         self._fresh = True
         return self.psi.expect_z(self.obs)[1]

@@ -242,7 +242,12 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
  * QSV_FLAG_CAPTURE_GRAPH: capture upload, counter reset, kernel and result
  * download in a hipGraph on a library-owned stream, and replay it on later
  * calls with the same batch shape (new angles are uploaded by the replay).
- * Synchronises before returning. */
+ * Synchronises before returning.
+ * Errors: a workgroup that waits for the previous pass of its circuit gives
+ * up after a bounded number of sleeps (about 2 s; the environment variable
+ * QSV_BATCH_SPIN_LIMIT, read at each launch or capture, sets the count), the
+ * rest of the launch drains without computing, and the call returns
+ * QSV_ERR_HIP with "spin limit" in qsv_last_error; out is then not written. */
 qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off,
                          const qsv_gate* g, const double* params, int64_t nparams,
                          const int64_t* term_off, const uint64_t* qmasks, const double* w,

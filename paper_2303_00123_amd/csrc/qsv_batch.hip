@@ -24,6 +24,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <map>
@@ -491,7 +492,12 @@ hipError_t launch_batch(qsv_ctx ctx, hipStream_t stream, const char* dev, const 
     unsigned grid = unsigned(per_cu) * unsigned(ctx->num_cus);
     if (grid > unsigned(nitems)) grid = unsigned(nitems);
     if (grid == 0) grid = 1;
-    const unsigned spin_limit = 1u << 22;   // x s_sleep(8): about 2 s before giving up
+    // x s_sleep(8): about 2 s before giving up; QSV_BATCH_SPIN_LIMIT overrides
+    // it (0 makes every wait that has to wait fail at once, so tests can drive
+    // the error path with every workgroup still exiting normally)
+    unsigned spin_limit = 1u << 22;
+    if (const char* sl = std::getenv("QSV_BATCH_SPIN_LIMIT"))
+        spin_limit = unsigned(std::strtoul(sl, nullptr, 10));
     hipLaunchKernelGGL((k_batch<R, K>), dim3(grid), dim3(kThreads), 0, stream,
                        static_cast<V*>(states), dev + L.plan,
                        reinterpret_cast<const BCirc*>(dev + L.circs),

@@ -115,3 +115,20 @@ def test_batch_rejects_bad_input(q, ctx):
     big = W.Circuit(25, [W.g1(0, W.H)], np.zeros(0), [((0,), 1.0)])
     with pytest.raises(q.QsvError):
         ctx.batch_run([big], q.QSV_C128)
+
+
+def test_batch_wait_failure_is_reported(q, ctx, monkeypatch):
+    """Failure path, forced from the host: with the dependency-wait bound set
+    to zero, every item that has to wait for the previous pass of its circuit
+    gives up at once, raises the batch's error flag and the rest of the
+    launch drains (no workgroup hangs).  The call reports the error; the next
+    normal call on the same context is correct."""
+    circs = mixed_batch(3) * 4
+    monkeypatch.setenv("QSV_BATCH_SPIN_LIMIT", "0")
+    with pytest.raises(q.QsvError, match="spin limit"):
+        ctx.batch_run(circs, q.QSV_C128)
+    monkeypatch.delenv("QSV_BATCH_SPIN_LIMIT")
+    got = ctx.batch_run(circs, q.QSV_C128)
+    ref = oracle_values(circs)
+    for b, c in enumerate(circs):
+        assert abs(got[b] - ref[b]) <= tol(c, 2), b

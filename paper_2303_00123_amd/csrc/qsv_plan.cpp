@@ -83,6 +83,9 @@ static size_t closure_count(const std::vector<int>& rem, size_t lim, const std::
 // pass takes the most gates (ties: fewer new bits, then circuit order),
 // until no gate's bits fit in the K positions.  This looks past the first
 // gates in circuit order, which an in-order greedy fill would commit to.
+// remaining gate count below which the planner searches the tail
+constexpr size_t kTailLookGates = 400;
+
 static uint64_t choose_bits(const std::vector<int>& rem, const std::vector<uint64_t>& masks, uint64_t S, int K) {
     const size_t lim = std::min(rem.size(), size_t(4096));
     for (;;) {
@@ -445,6 +448,63 @@ std::vector<PGate> prefuse(const std::vector<PGate>& gates) {
 
 void plan_pass_stages(int n, const std::vector<PGate>& gates, Pass& ps) { plan_stages(n, gates, ps); }
 
+// Passes the greedy planner needs for `rem` (bit sets only, no stages).
+static int count_passes(std::vector<int> rem, const std::vector<uint64_t>& masks, uint64_t low, int K) {
+    int np = 0;
+    std::vector<int> take, defer;
+    while (!rem.empty()) {
+        uint64_t S = choose_bits(rem, masks, low, K);
+        take.clear();
+        defer.clear();
+        greedy(rem, masks, S, K, true, take, defer);
+        rem.swap(defer);
+        ++np;
+    }
+    return np;
+}
+
+// Near the end of a circuit the pass-by-pass choice can leave a last pass
+// of a few gates that still costs a full read and write of the state.  When
+// few gates remain, try as this pass's bit set the completion of every
+// first gate choice (not only the best-scoring one) and keep the set after
+// which the fewest passes remain; ties keep the default choice.
+static uint64_t choose_bits_tail(const std::vector<int>& rem, const std::vector<uint64_t>& masks, uint64_t low,
+                                 int K, uint64_t S_def) {
+    auto passes_after = [&](uint64_t S) {
+        std::vector<int> take, defer;
+        greedy(rem, masks, S, K, true, take, defer);
+        return take.empty() ? 1 << 30 : 1 + count_passes(std::move(defer), masks, low, K);
+    };
+    int best_np = passes_after(S_def);
+    if (best_np <= 1) return S_def;
+    uint64_t best = S_def;
+    uint64_t tried[64];
+    int nt = 0;
+    uint64_t blocked = 0;
+    const int have = __builtin_popcountll(low);
+    for (size_t j = 0; j < rem.size() && nt < 64; ++j) {
+        const uint64_t gm = masks[size_t(rem[j])];
+        const uint64_t need = gm & ~low;
+        if (need && !(gm & blocked) && have + __builtin_popcountll(need) <= K) {
+            bool dup = false;
+            for (int c = 0; c < nt; ++c) dup |= tried[c] == need;
+            if (!dup) {
+                tried[nt++] = need;
+                const uint64_t S = choose_bits(rem, masks, low | need, K);
+                if (S != best) {
+                    const int np = passes_after(S);
+                    if (np < best_np) {
+                        best_np = np;
+                        best = S;
+                    }
+                }
+            }
+        }
+        if (need || (gm & blocked)) blocked |= gm;
+    }
+    return best;
+}
+
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {
     std::vector<Pass> passes;
     std::vector<uint64_t> masks(gates.size());
@@ -467,7 +527,9 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
 
     while (!rem.empty()) {
-        uint64_t S = choose_bits(rem, masks, (uint64_t(1) << L) - 1, K);
+        const uint64_t low = (uint64_t(1) << L) - 1;
+        uint64_t S = choose_bits(rem, masks, low, K);
+        if (rem.size() <= kTailLookGates) S = choose_bits_tail(rem, masks, low, K, S);
         std::vector<int> take, defer;
         take.reserve(rem.size());
         greedy(rem, masks, S, K, true, take, defer);

@@ -11,6 +11,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTermsPerPass = 16;
 constexpr int kMaxBlocks = 2048;
+// loads each thread keeps in flight; the sums keep the order of the plain
+// strided loop, so results do not depend on it
+constexpr int kUnroll = 4;
 
 struct ZMasks {
     uint64_t m[kTermsPerPass];
@@ -56,12 +59,21 @@ __global__ __launch_bounds__(kThreads) void k_zstr(const typename V2T<R>::type* 
     for (int t = 0; t < kTermsPerPass; ++t) acc[t] = 0.0;
     const uint64_t lo = uint64_t(blockIdx.x) * chunk;
     const uint64_t hi = lo + chunk < N ? lo + chunk : N;
-    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
-        const double p = prob<R>(s[x]);
+    auto add = [&](uint64_t x, const typename V2T<R>::type& v) {
+        const double p = prob<R>(v);
 #pragma unroll
         for (int t = 0; t < kTermsPerPass; ++t)
             if (t < zm.nt) acc[t] += (__popcll(x & zm.m[t]) & 1) ? -p : p;
+    };
+    uint64_t x = lo + threadIdx.x;
+    for (; x + (kUnroll - 1) * kThreads < hi; x += kUnroll * kThreads) {
+        typename V2T<R>::type v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[u] = s[x + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) add(x + u * kThreads, v[u]);
     }
+    for (; x < hi; x += kThreads) add(x, s[x]);
 #pragma unroll
     for (int t = 0; t < kTermsPerPass; ++t) red[t][threadIdx.x] = acc[t];
     block_tree<kTermsPerPass>(red, partials + size_t(blockIdx.x) * kTermsPerPass);
@@ -76,11 +88,20 @@ __global__ __launch_bounds__(kThreads) void k_split(const typename V2T<R>::type*
     double a0 = 0.0, a1 = 0.0;
     const uint64_t lo = uint64_t(blockIdx.x) * chunk;
     const uint64_t hi = lo + chunk < N ? lo + chunk : N;
-    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
-        const double q = prob<R>(s[x]);
+    auto add = [&](uint64_t x, const typename V2T<R>::type& v) {
+        const double q = prob<R>(v);
         if ((x >> p) & 1) a1 += q;
         else a0 += q;
+    };
+    uint64_t x = lo + threadIdx.x;
+    for (; x + (kUnroll - 1) * kThreads < hi; x += kUnroll * kThreads) {
+        typename V2T<R>::type v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[u] = s[x + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) add(x + u * kThreads, v[u]);
     }
+    for (; x < hi; x += kThreads) add(x, s[x]);
     red[0][threadIdx.x] = a0;
     red[1][threadIdx.x] = a1;
     block_tree<2>(red, partials + size_t(blockIdx.x) * 2);
@@ -96,11 +117,24 @@ __global__ __launch_bounds__(kThreads) void k_inner(const typename V2T<Ra>::type
     double re = 0.0, im = 0.0;
     const uint64_t lo = uint64_t(blockIdx.x) * chunk;
     const uint64_t hi = lo + chunk < N ? lo + chunk : N;
-    for (uint64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
-        const double ar = a[x].x, ai = a[x].y, br = b[x].x, bi = b[x].y;
+    auto add = [&](const typename V2T<Ra>::type& av, const typename V2T<Rb>::type& bv) {
+        const double ar = av.x, ai = av.y, br = bv.x, bi = bv.y;
         re += ar * br + ai * bi;
         im += ar * bi - ai * br;
+    };
+    uint64_t x = lo + threadIdx.x;
+    for (; x + (kUnroll - 1) * kThreads < hi; x += kUnroll * kThreads) {
+        typename V2T<Ra>::type va[kUnroll];
+        typename V2T<Rb>::type vb[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            va[u] = a[x + u * kThreads];
+            vb[u] = b[x + u * kThreads];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) add(va[u], vb[u]);
     }
+    for (; x < hi; x += kThreads) add(a[x], b[x]);
     red[0][threadIdx.x] = re;
     red[1][threadIdx.x] = im;
     block_tree<2>(red, partials + size_t(blockIdx.x) * 2);

@@ -194,6 +194,22 @@ def test_fusion_reduces_dispatches_on_brick_circuit():
     assert len(recs) < 0.7 * len(c.gates)
 
 
+def test_planner_tail_search_saves_passes():
+    """Near the end of a circuit the planner tries every first gate choice
+    for the pass's bit set; on the 30-qubit brick this leaves no short last
+    pass (20 passes, not 21), and the 28-qubit brick drops to 19."""
+    for n, seed, most in ((30, 3002, 20), (28, 1002, 19)):
+        c = W.layered_cnot_brick(n, 20, seed=seed)
+        recs, pas = q.plan_fused(c.n, c.gates)
+        assert int(pas.max()) + 1 <= most, n
+    # the search keeps the blocking rule: reordered circuit, same state
+    c = W.layered_cnot_brick(15, 12, seed=15)
+    _, order, _ = _check_plan(c, 11, 3)
+    re = W.Circuit(c.n, [c.gates[i] for i in order])
+    phi = W.random_state(c.n, 3)
+    assert np.max(np.abs(O.run(re, phi) - O.run(c, phi))) < 1e-13
+
+
 def _permutation_mix(n, ngates, seed):
     rng = np.random.default_rng(seed)
     X = np.array([[0, 1], [1, 0]], dtype=complex)

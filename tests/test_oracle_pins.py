@@ -460,3 +460,71 @@ def test_ry_rz_ladder_gradients():
     c = W.ry_rz_cnot_ladder(4, 2, rng)
     f, g = O.adjoint(c)
     assert np.max(np.abs(g - O.param_shift(c))) < 1e-12
+
+
+# ------------------------------------ gradients through general fixed gates
+_PAULI = {"X": W.X, "Y": W.Y, "Z": W.Z}
+
+
+def _dense_gate(n, g, params):
+    """Dense operator of one gate from kron products alone (eq. (1) literally;
+    rotations as matrix exponentials of their Pauli generator)."""
+    if g.kind == W.KIND_ROT:
+        u = scipy.linalg.expm(-0.5j * params[g.param] * _PAULI[g.axis])
+        return dense_1q(n, g.qubits[0], u)
+    if g.kind == W.KIND_1Q:
+        return dense_1q(n, g.qubits[0], g.matrix)
+    if g.kind == W.KIND_C1Q:
+        return dense_c1q(n, g.qubits[0], g.qubits[1], g.matrix, g.ctrl_state)
+    return dense_2q(n, g.qubits[0], g.qubits[1], g.matrix)
+
+
+def _dense_energy_and_grad(c):
+    """f = <0|U^dag O U|0> and df/dtheta_j from dense products:
+    d/dtheta exp(-i theta P/2) = (-i/2) P exp(-i theta P/2), carried through
+    the rest of the circuit as a second vector; df = 2 Re <psi| O |dpsi>."""
+    n = c.n
+    mats = [_dense_gate(n, g, c.params) for g in c.gates]
+    diag = np.zeros(2 ** n)
+    for qs, w in c.observable:
+        ops = [W.Z if q in qs else W.I2 for q in range(n)]
+        diag += w * np.real(np.diag(kron_all(*ops)))
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1.0
+    prefix = []
+    for m in mats:
+        prefix.append(psi)
+        psi = m @ psi
+    grad = np.zeros(c.params.size)
+    for k, g in enumerate(c.gates):
+        if g.kind != W.KIND_ROT:
+            continue
+        d = dense_1q(n, g.qubits[0], -0.5j * _PAULI[g.axis]) @ (mats[k] @ prefix[k])
+        for m in mats[k + 1:]:
+            d = m @ d
+        grad[g.param] += 2.0 * np.real(np.vdot(psi, diag * d))
+    return float(np.real(np.vdot(psi, diag * psi))), grad
+
+
+@pytest.mark.parametrize("n,layers,seed", [(4, 2, 31), (5, 2, 32), (6, 1, 33)])
+def test_adjoint_through_general_fixed_gates(n, layers, seed):
+    """The adjoint sweep rewinds every fixed gate with its conjugate
+    transpose.  With Haar 1q, Haar 2q (both qubit orders) and controlled Haar
+    gates (control state 0 and 1) in the circuit, a missing conjugation or
+    transposition in that rewind changes the gradient; the dense-matrix
+    derivative above and the parameter-shift rule (forward runs only) both
+    pin it."""
+    c = W.mixed_param_circuit(n, layers, seed)
+    kinds = {(g.kind, g.ctrl_state if g.kind == W.KIND_C1Q else None) for g in c.gates}
+    assert {(W.KIND_1Q, None), (W.KIND_2Q, None), (W.KIND_C1Q, 0), (W.KIND_C1Q, 1)} <= kinds
+    assert any(g.kind == W.KIND_2Q and g.qubits[0] > g.qubits[1] for g in c.gates)
+    for g in c.gates:   # none of the fixed gates is its own adjoint
+        if g.kind != W.KIND_ROT:
+            assert np.max(np.abs(g.matrix - g.matrix.conj().T)) > 1e-3
+    f_ref, g_ref = _dense_energy_and_grad(c)
+    f, g = O.adjoint(c)
+    wsum = max(1.0, sum(abs(w) for _, w in c.observable))
+    assert abs(f - f_ref) < 1e-13 * wsum
+    assert np.max(np.abs(g - g_ref)) < 1e-12 * wsum
+    assert np.max(np.abs(O.param_shift(c) - g_ref)) < 1e-12 * wsum
+    assert np.max(np.abs(O.finite_diff(c, h=1e-6) - g_ref)) < 1e-6 * wsum

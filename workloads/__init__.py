@@ -242,6 +242,42 @@ def config5(n: int = 24, layers: int = 10, seed: int = 1005) -> Circuit:
     return hea_cz_ring(n, layers, seed)
 
 
+def mixed_param_circuit(n: int, layers: int, seed: int) -> Circuit:
+    """Rotations interleaved with fixed gates that are not their own inverse,
+    for gradient checks through general gates.  Each layer: a rotation on
+    every qubit (axis X, Y, Z in turn), a Haar 1q gate on a random qubit,
+    Haar 2q gates on a random pair in ascending and in descending qubit
+    order, controlled Haar gates with control state 0 and 1 on random
+    ordered pairs, then one more rotation.  Every parameter drives one
+    rotation.  Observable: sum_i w_i Z_i Z_{i+1} plus w_n Z_0, w ~ N(0, 1)."""
+    if n < 2:
+        raise ValueError("mixed_param_circuit needs n >= 2")
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = []
+    params: List[float] = []
+
+    def rot(q: int, axis: str):
+        gates.append(grot(q, axis, len(params)))
+        params.append(rng.uniform(0.0, 2.0 * np.pi))
+
+    for layer in range(layers):
+        for q in range(n):
+            rot(q, AXES[(q + layer) % 3])
+        gates.append(g1(int(rng.integers(n)), haar_unitary(2, rng)))
+        a, b = sorted(int(x) for x in rng.choice(n, size=2, replace=False))
+        gates.append(g2(a, b, haar_unitary(4, rng)))
+        a, b = sorted(int(x) for x in rng.choice(n, size=2, replace=False))
+        gates.append(g2(b, a, haar_unitary(4, rng)))
+        for cs in (0, 1):
+            qc, qt = (int(x) for x in rng.choice(n, size=2, replace=False))
+            gates.append(gc(qc, qt, haar_unitary(2, rng), cs))
+        rot(int(rng.integers(n)), AXES[layer % 3])
+    w = rng.standard_normal(n)
+    obs = [((i, i + 1), float(w[i])) for i in range(n - 1)] + [((0,), float(w[n - 1]))]
+    return Circuit(n, gates, np.asarray(params, dtype=np.float64), obs,
+                   f"mixed_param_n{n}_l{layers}")
+
+
 def qft(n: int) -> Circuit:
     """QFT circuit as printed in Fig. 1 of the paper: for each i, H(i) then
     controlled-phase CP(ctrl=j+i-1, tgt=i, theta=-2 pi / 2^j) for j=2..n-i;

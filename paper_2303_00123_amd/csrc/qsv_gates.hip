@@ -54,6 +54,35 @@ __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* 
     }
 }
 
+// Pair update of the pair kernels.  PK_DENSE: the 2x2 matvec of Algs. 1-2.
+// Gates with more structure need less (Sec. 2.1 writes X, Y and Z out as
+// such special cases): PK_ANTI, an anti-diagonal matrix [[0, u01], [u10, 0]]
+// (Y and phased X): each output is one input times a phase, no sums;
+// PK_SWAP, X itself: the pair is exchanged, data movement only (for a
+// controlled X, Sec. 2.2's CNOT, half the pairs are exchanged).
+enum { PK_DENSE = 0, PK_ANTI = 1, PK_SWAP = 2 };
+
+template <typename R, typename V>
+__device__ __forceinline__ V cmul_s(const V& a, R dr, R di) {
+    V o;
+    o.x = fmaR(-a.y, di, a.x * dr);
+    o.y = fmaR(a.y, dr, a.x * di);
+    return o;
+}
+
+template <typename R, int PK, typename V>
+__device__ __forceinline__ void pair_op(const R* u, const V& a, const V& b, V& oa, V& ob) {
+    if constexpr (PK == PK_DENSE) {
+        mv2(u, a, b, oa, ob);
+    } else if constexpr (PK == PK_ANTI) {
+        oa = cmul_s(b, u[2], u[3]);
+        ob = cmul_s(a, u[4], u[5]);
+    } else {
+        oa = b;
+        ob = a;
+    }
+}
+
 // ------------------------------------------------------------- Alg. 1
 // Pair j -> a_j = insert0(j, p), b_j = a_j + 2^p; 2x2 matvec in place.
 // CTRL: Alg. 2 with its control at a low index bit pc (below the 128-byte
@@ -61,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_init_basis(typename V2T<R>::type* 
 // where bit pc of a_j equals cs.  The pairs Alg. 2 would skip share lines
 // with the ones it moves, so HBM carries the whole state either way; this
 // form keeps every access a full, contiguous line.
-template <typename R, bool CTRL = false>
+template <typename R, bool CTRL = false, int PK = PK_DENSE>
 __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __restrict__ s,
                                                       uint64_t npairs, int p, M2<R> u, int pc = 0,
                                                       int cs = 0) {
@@ -87,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
             if (j < npairs) {
                 const uint64_t ia = insert0(j, p);
                 V oa, ob;
-                mv2(u.v, a[k], b[k], oa, ob);
+                pair_op<R, PK>(u.v, a[k], b[k], oa, ob);
                 if (CTRL && int((ia >> pc) & 1) != cs) {
                     oa = a[k];
                     ob = b[k];
@@ -102,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
 // ------------------------------------------------------------- Alg. 2
 // Pair j -> zero bits inserted at both positions (lower first), the control
 // bit set to cs, b_j = a_j + 2^pt.
-template <typename R>
+template <typename R, int PK = PK_DENSE>
 __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __restrict__ s,
                                                        uint64_t npairs, int plo, int phi, int pc,
                                                        int pt, int cs, M2<R> u) {
@@ -129,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
             if (j < npairs) {
                 const uint64_t ia = insert0(insert0(j, plo), phi) | wc;
                 V oa, ob;
-                mv2(u.v, a[k], b[k], oa, ob);
+                pair_op<R, PK>(u.v, a[k], b[k], oa, ob);
                 st_nt(s + ia, oa);
                 st_nt(s + ia + wt, ob);
             }
@@ -178,6 +207,78 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
     }
 }
 
+// ------------------------------------------------ diagonal gates (one pass)
+// A diagonal gate (Z, S, T, P, RZ, CZ, CP, ...) multiplies each amplitude by
+// one entry of its diagonal and mixes nothing.  Item j names amplitude
+//   x = j with zero bits inserted at positions f0 < f1 (nfix of them), then
+//       the fixed bit values `fixval` set,
+// which is multiplied by d[2 * bit(x, sa) + bit(x, sb)].  Fixing a bit
+// restricts the pass to the amplitudes the gate changes: for P(theta) on
+// position p, bit p = 1 (half the state); for a controlled phase, the
+// control bit = cs and the target bit = 1 (a quarter).  With no fixed bits
+// it is one linear pass over the state.
+template <typename R>
+struct D4 { R v[8]; };   // four complex entries (re, im)
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_diag(typename V2T<R>::type* __restrict__ s,
+                                                   uint64_t items, int nfix, int f0, int f1,
+                                                   uint64_t fixval, int sa, int sb, D4<R> d) {
+    using V = typename V2T<R>::type;
+    constexpr int P = PPT<R>::value;
+    constexpr uint64_t BS = uint64_t(kThreads) * P;
+    for (uint64_t blk = blockIdx.x; blk * BS < items; blk += gridDim.x) {
+        const uint64_t j0 = blk * BS + threadIdx.x;
+        V a[P];
+        uint64_t xs[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            uint64_t x = j;
+            if (nfix > 0) x = insert0(x, f0);
+            if (nfix > 1) x = insert0(x, f1);
+            xs[k] = x | fixval;
+            if (j < items) a[k] = ld_nt(s + xs[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const uint64_t j = j0 + uint64_t(k) * kThreads;
+            if (j < items) {
+                const int e = int(((xs[k] >> sa) & 1) * 2 + ((xs[k] >> sb) & 1));
+                st_nt(s + xs[k], cmul_s(a[k], d.v[2 * e], d.v[2 * e + 1]));
+            }
+        }
+    }
+}
+
+// ------------------------------------------- 2-qubit permutation (one pass)
+// A 2-qubit gate whose matrix is a permutation with unit entries (SWAP of
+// Sec. 2.3, CNOT written as a 4x4, ...) moves amplitudes and computes
+// nothing.  For quad j (zero bits inserted at plo < phi) output element r
+// (local index 2*x_qa + x_qb) takes input element src[r]; only the elements
+// that move are read and written: SWAP touches two of the four.
+struct Perm4 { int src[4]; };
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_perm2q(typename V2T<R>::type* __restrict__ s,
+                                                     uint64_t nquads, int plo, int phi, int pa,
+                                                     int pb, Perm4 pm) {
+    using V = typename V2T<R>::type;
+    const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
+    const uint64_t off[4] = {0, wb, wa, wa + wb};
+    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < nquads;
+         j += uint64_t(gridDim.x) * kThreads) {
+        const uint64_t i0 = insert0(insert0(j, plo), phi);
+        V v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (pm.src[r] != r) v[r] = ld_nt(s + i0 + off[pm.src[r]]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (pm.src[r] != r) st_nt(s + i0 + off[r], v[r]);
+    }
+}
+
 template <typename R>
 unsigned grid_for(uint64_t items, int per_thread) {
     const uint64_t per_block = uint64_t(kThreads) * per_thread;
@@ -208,14 +309,84 @@ hipError_t init_basis_t(qsv_ctx ctx, void* s, int n, uint64_t b) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------ structure of a gate matrix
+// Exact tests on the FP64 entries (a complex64 state rounds them once, and
+// 0 and 1 round to themselves).
+inline bool czero(const double* u, int i) { return u[2 * i] == 0.0 && u[2 * i + 1] == 0.0; }
+inline bool cone(const double* u, int i) { return u[2 * i] == 1.0 && u[2 * i + 1] == 0.0; }
+inline bool is_diag2(const double* u) { return czero(u, 1) && czero(u, 2); }
+inline bool is_anti2(const double* u) { return czero(u, 0) && czero(u, 3); }
+inline bool is_x2(const double* u) { return is_anti2(u) && cone(u, 1) && cone(u, 2); }
+inline bool is_diag4(const double* u) {
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            if (r != c && !czero(u, 4 * r + c)) return false;
+    return true;
+}
+// A permutation matrix with unit entries: src[r] = the column of row r's 1.
+inline bool is_perm4(const double* u, int* src) {
+    int seen = 0;
+    for (int r = 0; r < 4; ++r) {
+        src[r] = -1;
+        for (int c = 0; c < 4; ++c) {
+            if (cone(u, 4 * r + c)) {
+                if (src[r] >= 0) return false;
+                src[r] = c;
+            } else if (!czero(u, 4 * r + c)) {
+                return false;
+            }
+        }
+        if (src[r] < 0 || (seen >> src[r]) & 1) return false;
+        seen |= 1 << src[r];
+    }
+    return true;
+}
+
+template <typename R>
+constexpr int line_bits() { return sizeof(R) == 8 ? 3 : 4; }   // amplitudes per 128-byte line
+
+// Launch k_diag over `items` amplitudes; d holds the four entries selected
+// by 2 * bit(sa) + bit(sb) as (re, im) doubles.
+template <typename R>
+hipError_t diag_t(qsv_ctx ctx, void* s, uint64_t items, int nfix, int f0, int f1, uint64_t fixval,
+                  int sa, int sb, const double* d) {
+    using V = typename V2T<R>::type;
+    D4<R> dd;
+    for (int i = 0; i < 8; ++i) dd.v[i] = R(d[i]);
+    prof_before(ctx, sizeof(R) == 8 ? "diag_c128" : "diag_c64", 2.0 * double(items) * sizeof(V));
+    hipLaunchKernelGGL(k_diag<R>, dim3(grid_for<R>(items, PPT<R>::value)), dim3(kThreads), 0,
+                       ctx->stream, static_cast<V*>(s), items, nfix, f0, f1, fixval, sa, sb, dd);
+    prof_after(ctx);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t apply1q_t(qsv_ctx ctx, void* s, int n, int p, const double* u) {
     using V = typename V2T<R>::type;
-    const uint64_t np = uint64_t(1) << (n - 1);
-    prof_before(ctx, sizeof(R) == 8 ? "apply1q_c128" : "apply1q_c64",
-                2.0 * double(uint64_t(1) << n) * sizeof(V));
-    hipLaunchKernelGGL((k_apply1q<R, false>), dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
-                       ctx->stream, static_cast<V*>(s), np, p, to_m2<R>(u), 0, 0);
+    const uint64_t N = uint64_t(1) << n;
+    const uint64_t np = N >> 1;
+    if (is_diag2(u)) {
+        // entries d0 (bit p = 0) and d1 (bit p = 1) at selector values 0 and 3
+        const double d[8] = {u[0], u[1], 0, 0, 0, 0, u[6], u[7]};
+        if (cone(u, 0) && p >= line_bits<R>())   // Z, S, T, P(theta): only bit p = 1 changes
+            return diag_t<R>(ctx, s, np, 1, p, 0, uint64_t(1) << p, p, p, d);
+        return diag_t<R>(ctx, s, N, 0, 0, 0, 0, p, p, d);
+    }
+    const bool anti = is_anti2(u), x = is_x2(u);
+    prof_before(ctx, x ? (sizeof(R) == 8 ? "perm1q_c128" : "perm1q_c64")
+                       : anti ? (sizeof(R) == 8 ? "anti1q_c128" : "anti1q_c64")
+                              : (sizeof(R) == 8 ? "apply1q_c128" : "apply1q_c64"),
+                2.0 * double(N) * sizeof(V));
+    const dim3 grid(grid_for<R>(np, GatePairs<R>::value));
+    if (x)
+        hipLaunchKernelGGL((k_apply1q<R, false, PK_SWAP>), grid, dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(s), np, p, to_m2<R>(u), 0, 0);
+    else if (anti)
+        hipLaunchKernelGGL((k_apply1q<R, false, PK_ANTI>), grid, dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(s), np, p, to_m2<R>(u), 0, 0);
+    else
+        hipLaunchKernelGGL((k_apply1q<R, false>), grid, dim3(kThreads), 0, ctx->stream,
+                           static_cast<V*>(s), np, p, to_m2<R>(u), 0, 0);
     prof_after(ctx);
     return hipGetLastError();
 }
@@ -223,20 +394,59 @@ hipError_t apply1q_t(qsv_ctx ctx, void* s, int n, int p, const double* u) {
 template <typename R>
 hipError_t applyc1q_t(qsv_ctx ctx, void* s, int n, int pc, int pt, int cs, const double* u) {
     using V = typename V2T<R>::type;
-    const uint64_t np = uint64_t(1) << (n - 2);
+    const uint64_t N = uint64_t(1) << n;
+    const uint64_t np = N >> 2;
     const int plo = pc < pt ? pc : pt, phi = pc < pt ? pt : pc;
-    prof_before(ctx, sizeof(R) == 8 ? "applyc1q_c128" : "applyc1q_c64",
-                double(uint64_t(1) << n) * sizeof(V));
+    const int lb = line_bits<R>();
+    if (is_diag2(u)) {
+        // U = diag(d0, d1) on the target where the control bit equals cs
+        if (cone(u, 0) && pc >= lb && pt >= lb) {   // CZ, CP: a quarter of the state changes
+            const double d[8] = {0, 0, 0, 0, 0, 0, u[6], u[7]};
+            return diag_t<R>(ctx, s, np, 2, plo, phi, (uint64_t(cs) << pc) | (uint64_t(1) << pt), pt,
+                             pt, d);
+        }
+        if (pc >= lb) {   // the half with the control bit set to cs
+            const double d[8] = {u[0], u[1], 0, 0, 0, 0, u[6], u[7]};
+            return diag_t<R>(ctx, s, 2 * np, 1, pc, 0, uint64_t(cs) << pc, pt, pt, d);
+        }
+        // control below the line: every line is touched; selector 2*c + t
+        double d[8] = {1, 0, 1, 0, 1, 0, 1, 0};
+        d[4 * cs + 0] = u[0];
+        d[4 * cs + 1] = u[1];
+        d[4 * cs + 2] = u[6];
+        d[4 * cs + 3] = u[7];
+        return diag_t<R>(ctx, s, N, 0, 0, 0, 0, pc, pt, d);
+    }
+    const bool anti = is_anti2(u), x = is_x2(u);
+    prof_before(ctx, x ? (sizeof(R) == 8 ? "cperm1q_c128" : "cperm1q_c64")
+                       : anti ? (sizeof(R) == 8 ? "canti1q_c128" : "canti1q_c64")
+                              : (sizeof(R) == 8 ? "applyc1q_c128" : "applyc1q_c64"),
+                double(N) * sizeof(V));
     // a control below the 128-byte line: the whole state moves anyway, so
     // move it in full lines (see k_apply1q)
-    const int line_bits = sizeof(R) == 8 ? 3 : 4;
-    if (pc < line_bits)
-        hipLaunchKernelGGL((k_apply1q<R, true>), dim3(grid_for<R>(2 * np, GatePairs<R>::value)),
-                           dim3(kThreads), 0, ctx->stream, static_cast<V*>(s), 2 * np, pt,
-                           to_m2<R>(u), pc, cs);
-    else
-        hipLaunchKernelGGL(k_applyc1q<R>, dim3(grid_for<R>(np, GatePairs<R>::value)), dim3(kThreads), 0,
-                           ctx->stream, static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
+    if (pc < lb) {
+        const dim3 grid(grid_for<R>(2 * np, GatePairs<R>::value));
+        if (x)
+            hipLaunchKernelGGL((k_apply1q<R, true, PK_SWAP>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), 2 * np, pt, to_m2<R>(u), pc, cs);
+        else if (anti)
+            hipLaunchKernelGGL((k_apply1q<R, true, PK_ANTI>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), 2 * np, pt, to_m2<R>(u), pc, cs);
+        else
+            hipLaunchKernelGGL((k_apply1q<R, true>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), 2 * np, pt, to_m2<R>(u), pc, cs);
+    } else {
+        const dim3 grid(grid_for<R>(np, GatePairs<R>::value));
+        if (x)
+            hipLaunchKernelGGL((k_applyc1q<R, PK_SWAP>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
+        else if (anti)
+            hipLaunchKernelGGL((k_applyc1q<R, PK_ANTI>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
+        else
+            hipLaunchKernelGGL((k_applyc1q<R>), grid, dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), np, plo, phi, pc, pt, cs, to_m2<R>(u));
+    }
     prof_after(ctx);
     return hipGetLastError();
 }
@@ -244,10 +454,30 @@ hipError_t applyc1q_t(qsv_ctx ctx, void* s, int n, int pc, int pt, int cs, const
 template <typename R>
 hipError_t apply2q_t(qsv_ctx ctx, void* s, int n, int pa, int pb, const double* u) {
     using V = typename V2T<R>::type;
-    const uint64_t nq = uint64_t(1) << (n - 2);
+    const uint64_t N = uint64_t(1) << n;
+    const uint64_t nq = N >> 2;
     const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
-    prof_before(ctx, sizeof(R) == 8 ? "apply2q_c128" : "apply2q_c64",
-                2.0 * double(uint64_t(1) << n) * sizeof(V));
+    const int lb = line_bits<R>();
+    if (is_diag4(u)) {
+        // entry r = 2*x_qa + x_qb of the diagonal, selected by bits (pa, pb)
+        const double d[8] = {u[0], u[1], u[10], u[11], u[20], u[21], u[30], u[31]};
+        if (cone(u, 0) && cone(u, 5) && cone(u, 10) && pa >= lb && pb >= lb)   // CZ, CP as a 4x4
+            return diag_t<R>(ctx, s, nq, 2, plo, phi, (uint64_t(1) << pa) | (uint64_t(1) << pb), pa,
+                             pb, d);
+        return diag_t<R>(ctx, s, N, 0, 0, 0, 0, pa, pb, d);
+    }
+    Perm4 pm;
+    if (is_perm4(u, pm.src)) {
+        int moved = 0;
+        for (int r = 0; r < 4; ++r) moved += pm.src[r] != r;
+        prof_before(ctx, sizeof(R) == 8 ? "perm2q_c128" : "perm2q_c64",
+                    2.0 * double(moved) * double(nq) * sizeof(V));
+        hipLaunchKernelGGL(k_perm2q<R>, dim3(capped_grid((nq + kThreads - 1) / kThreads)), dim3(kThreads),
+                           0, ctx->stream, static_cast<V*>(s), nq, plo, phi, pa, pb, pm);
+        prof_after(ctx);
+        return hipGetLastError();
+    }
+    prof_before(ctx, sizeof(R) == 8 ? "apply2q_c128" : "apply2q_c64", 2.0 * double(N) * sizeof(V));
     hipLaunchKernelGGL(k_apply2q<R>, dim3(grid_for<R>(nq, GateQuads<R>::value)), dim3(kThreads), 0,
                        ctx->stream, static_cast<V*>(s), nq, plo, phi, pa, pb, to_m4<R>(u));
     prof_after(ctx);

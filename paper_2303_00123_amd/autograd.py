@@ -5,7 +5,9 @@
     f.backward()                               # theta.grad <- df/dtheta
 
 f(theta) = <0..0| U(theta)^dagger O U(theta) |0..0> with O a weighted sum of
-Z strings (the cost of the variational examples of Sec. 5).  The forward
+Z strings: the cost function of a variational (parametrised-circuit)
+algorithm.  The paper's simulator evaluates such circuits forward only; the
+gradient here is the adjoint method of Jones and Gacon (arXiv:2009.02823).  The forward
 pass runs the circuit with the fused tile passes and reduces O on the GPU;
 the backward pass rewinds the stored state together with the co-state
 O|psi> in one sweep (qsv_adjoint), so one backward costs about as much as a

@@ -54,7 +54,7 @@ static void load_cache(qsv_ctx ctx) {
         int dtype = 0, tb = 0, lb = 0;
         if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"key\": \"%llx\", \"dtype\": %d, \"tile_bits\": %d, \"low_bits\": %d",
                         a, &key, &dtype, &tb, &lb) == 5 &&
-            arch == a && tb >= kMinTileBits && tb <= 12 && lb >= 0 && lb <= tb - 2)
+            arch == a && tb >= kMinTileBits && tb <= kMaxTileBits && lb >= 0 && lb <= tb - 2)
             ctx->tuned[full_key(key, dtype)] = std::make_pair(tb, lb);
     }
     std::fclose(f);

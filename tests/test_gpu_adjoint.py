@@ -98,3 +98,55 @@ def test_config5_adjoint_vs_gpu_parameter_shift(q, ctx):
     p64, l64 = q.State(ctx, c.n, q.QSV_C64), q.State(ctx, c.n, q.QSV_C64)
     g64 = q.adjoint(p64, l64, c.gates, c.params, c.observable)[1]
     assert np.max(np.abs(g64 - g)) <= 1e-4 * wsum(c)
+
+
+@pytest.mark.parametrize("n,layers,seed", [(12, 3, 41), (14, 3, 42), (15, 4, 43)])
+def test_adjoint_through_general_fixed_gates(q, ctx, n, layers, seed):
+    """Rotations interleaved with Haar 1q, Haar 2q (both qubit orders) and
+    controlled Haar gates (control state 0 and 1), none of them its own
+    inverse: the sweep rewinds each with its conjugate transpose.  Fused and
+    one kernel per gate, complex128 and complex64, against the oracle's
+    adjoint sweep (pinned by dense-matrix derivatives) and its parameter
+    shift."""
+    c = W.mixed_param_circuit(n, layers, seed)
+    f_ref, g_ref = O.adjoint(c)
+    tol = 1e-10 * wsum(c)
+    psi, lam = q.State(ctx, c.n), q.State(ctx, c.n)
+    for flags in (q.FLAG_FORWARD, q.FLAG_FORWARD | q.FLAG_NO_FUSE):
+        f, g = q.adjoint(psi, lam, c.gates, c.params, c.observable, flags=flags)
+        assert abs(f - f_ref) <= 1e-12 * wsum(c), flags
+        assert np.max(np.abs(g - g_ref)) <= tol, flags
+        v = psi.to_numpy()   # rewound through every gate: back to |0...0>
+        assert abs(v[0] - 1.0) <= 1e-10 and np.max(np.abs(v[1:])) <= 1e-10, flags
+    sel = list(range(0, len(c.params), 5))
+    assert np.max(np.abs(g[sel] - O.param_shift(c, sel))) <= tol
+    p64, l64 = q.State(ctx, c.n, q.QSV_C64), q.State(ctx, c.n, q.QSV_C64)
+    for flags in (q.FLAG_FORWARD, q.FLAG_FORWARD | q.FLAG_NO_FUSE):
+        f3, g3 = q.adjoint(p64, l64, c.gates, c.params, c.observable, flags=flags)
+        assert abs(f3 - f_ref) <= 1e-5 * wsum(c), flags
+        assert np.max(np.abs(g3 - g_ref)) <= 1e-4 * wsum(c), flags
+    for s in (psi, lam, p64, l64):
+        s.free()
+
+
+@pytest.mark.parametrize("dt_name", ["c128", "c64"])
+def test_config5_ansatz_20_qubits_vs_oracle_adjoint(q, ctx, dt_name):
+    """The configuration's ansatz (10 layers of RY, RZ on every qubit + CZ
+    ring, open-chain ZZ observable with N(0,1) weights) at 20 qubits, 400
+    parameters: every gradient component of the fused sweep against one
+    FP64 oracle adjoint sweep (the 24-qubit sweep takes minutes on the host),
+    and a sample against the oracle's parameter shift."""
+    c = W.hea_cz_ring(20, 10, seed=1005)
+    f_ref, g_ref = O.adjoint(c)
+    dt = q.QSV_C128 if dt_name == "c128" else q.QSV_C64
+    psi, lam = q.State(ctx, c.n, dt), q.State(ctx, c.n, dt)
+    f, g = q.adjoint(psi, lam, c.gates, c.params, c.observable)
+    tv, tg = (1e-12, 1e-10) if dt == q.QSV_C128 else (1e-5, 1e-4)
+    assert abs(f - f_ref) <= tv * wsum(c)
+    assert np.max(np.abs(g - g_ref)) <= tg * wsum(c)
+    if dt == q.QSV_C128:
+        sel = [0, 1, 57, 199, 398, 399]
+        assert np.max(np.abs(g[sel] - O.param_shift(c, sel))) <= tg * wsum(c)
+    print(f"20-qubit ansatz {dt_name}: max |d grad| = {np.max(np.abs(g - g_ref)):.3e}", flush=True)
+    psi.free()
+    lam.free()

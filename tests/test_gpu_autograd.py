@@ -91,3 +91,21 @@ def test_optimiser_step_lowers_energy(torch, AG):
     # the oracle agrees with the final value
     cf = W.Circuit(c.n, c.gates, th.detach().numpy().copy(), c.observable)
     assert abs(ev(th.detach()).item() - O.energy(cf)) <= 1e-12 * wsum(c)
+
+
+@pytest.mark.parametrize("dtype_name", ["c128", "c64"])
+def test_grad_through_general_fixed_gates(torch, AG, dtype_name):
+    """The autograd wrapper on a circuit whose fixed gates (Haar 1q, Haar 2q
+    in both qubit orders, controlled Haar with control state 0 and 1) are
+    not their own inverses, against the oracle's adjoint sweep."""
+    from paper_2303_00123_amd import QSV_C128, QSV_C64
+    c = W.mixed_param_circuit(13, 3, seed=26)
+    dt = QSV_C128 if dtype_name == "c128" else QSV_C64
+    ev = AG.Expectation(c.n, c.gates, c.observable, dtype=dt)
+    th = torch.tensor(c.params, dtype=torch.float64, requires_grad=True)
+    f = ev(th)
+    f.backward()
+    f_ref, g_ref = O.adjoint(c)
+    tv, tg = (1e-12, 1e-10) if dt == QSV_C128 else (1e-5, 1e-4)
+    assert abs(f.item() - f_ref) <= tv * wsum(c)
+    assert np.max(np.abs(th.grad.numpy() - g_ref)) <= tg * wsum(c)

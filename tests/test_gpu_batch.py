@@ -100,11 +100,33 @@ def test_config4_batch_vs_single_state_path(q, ctx, dtype):
         ref = st.expect_z(c.observable)[1]
         st.free()
         assert abs(got[b] - ref) <= (1e-11 if dtype == 2 else 1e-5 * c.n), (b, c.n)
-    # and a few against the oracle
-    for b in (0, 1, 2):
-        c = circs[b]
-        if c.n <= 16:
-            assert abs(got[b] - O.expect_obs(O.run(c), c.observable)) <= (1e-11 if dtype == 2 else 1e-5 * c.n)
+
+
+@pytest.fixture(scope="module")
+def config4_oracle():
+    """<sum_i Z_i> of every config-4 circuit (256 circuits, 12..20 qubits)
+    from the FP64 oracle: about a minute on the host, shared by both dtypes."""
+    circs = W.config4()
+    vals = []
+    for b, c in enumerate(circs):
+        vals.append(O.expect_obs(O.run(c), c.observable))
+        if b % 64 == 63:
+            print(f"config-4 oracle: {b + 1}/{len(circs)} circuits", flush=True)
+    return circs, np.array(vals)
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_config4_every_circuit_vs_oracle(q, ctx, config4_oracle, dtype):
+    """All 256 config-4 circuits (12..20 qubits, every width present) in one
+    batch launch against the FP64 oracle's final state and observable:
+    complex128 to 1e-11, complex64 to 1e-5 per qubit of the observable."""
+    circs, ref = config4_oracle
+    assert {c.n for c in circs} == set(range(12, 21))
+    got = ctx.batch_run(circs, dtype)
+    for b, c in enumerate(circs):
+        assert abs(got[b] - ref[b]) <= (1e-11 if dtype == 2 else 1e-5 * c.n), (b, c.n, got[b], ref[b])
+    err = np.max(np.abs(got - ref))
+    print(f"config-4 batch, dtype {dtype}: max |d <sum Z>| = {err:.3e}", flush=True)
 
 
 def test_batch_rejects_bad_input(q, ctx):
@@ -132,3 +154,30 @@ def test_batch_wait_failure_is_reported(q, ctx, monkeypatch):
     ref = oracle_values(circs)
     for b, c in enumerate(circs):
         assert abs(got[b] - ref[b]) <= tol(c, 2), b
+
+
+def test_tune_cache_file_reloads_in_a_fresh_context(q, tmp_path, monkeypatch):
+    """QSV_TUNE_CACHE: a tuned choice written by one context is read back by
+    a fresh one, which then does not tune again (no new line in the file).
+    The stored line is rewritten to 2^13-amplitude tiles, the complex64
+    default shape, to check that the reader accepts the largest tile."""
+    import json
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("QSV_TUNE_CACHE", str(path))
+    circs = mixed_batch(4)
+    ref = oracle_values(circs)
+    c1 = q.Context()
+    got = c1.batch_run(circs, q.QSV_C64, flags=q.FLAG_TUNE)
+    c1.close()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["dtype"] == q.QSV_C64
+    rec["tile_bits"], rec["low_bits"] = 13, 4
+    path.write_text(json.dumps(rec) + "\n")
+    c2 = q.Context()
+    got2 = c2.batch_run(circs, q.QSV_C64, flags=q.FLAG_TUNE)
+    c2.close()
+    assert len(path.read_text().splitlines()) == 1   # loaded, not tuned again
+    for b, c in enumerate(circs):
+        assert abs(got[b] - ref[b]) <= tol(c, 1) and abs(got2[b] - ref[b]) <= tol(c, 1), b

@@ -528,3 +528,37 @@ def test_adjoint_through_general_fixed_gates(n, layers, seed):
     assert np.max(np.abs(g - g_ref)) < 1e-12 * wsum
     assert np.max(np.abs(O.param_shift(c) - g_ref)) < 1e-12 * wsum
     assert np.max(np.abs(O.finite_diff(c, h=1e-6) - g_ref)) < 1e-6 * wsum
+
+
+# ------------------------------------------- Trotter (Hamiltonian) circuit
+def test_trotter_block_is_xx_zz_exponential():
+    """CNOT . (RX(a) on the control, RZ(b) on the target) . CNOT equals
+    exp(-i a/2 X(x)X) exp(-i b/2 Z(x)Z): conjugation by CNOT maps X(x)I to
+    X(x)X and I(x)Z to Z(x)Z.  The oracle runs the gate sequence; the closed
+    form is two matrix exponentials."""
+    a, b = 0.83, 2.41
+    XX = np.kron(W.X, W.X)
+    ZZ = np.kron(W.Z, W.Z)
+    ref_op = scipy.linalg.expm(-0.5j * a * XX) @ scipy.linalg.expm(-0.5j * b * ZZ)
+    c = W.Circuit(2, [W.cnot(0, 1), W.grot(0, "X", 0), W.grot(1, "Z", 1), W.cnot(0, 1)],
+                  np.array([a, b]))
+    for seed in (1, 2, 3):
+        s = _rand_state(2, 300 + seed)
+        assert np.max(np.abs(O.run(c, state=s) - ref_op @ s)) < 1e-15
+
+
+@pytest.mark.parametrize("n,steps", [(4, 2), (5, 1), (6, 2)])
+def test_trotter_circuit_vs_dense(n, steps):
+    """The Trotter generator's circuit through the oracle against the product
+    of its gates' dense kron operators; its layout follows the figure: two
+    RZ columns and four gates per nearest-neighbour pair per step, then a
+    closing RZ on the odd-block qubits."""
+    c = W.trotter_tfxy(n, steps, seed=40 + n)
+    npairs = n - 1
+    assert len(c.gates) == steps * (2 * n + 4 * npairs) + 2 * ((n - 1) // 2)
+    assert c.params.size == sum(g.kind == W.KIND_ROT for g in c.gates)
+    s = _rand_state(n, 50 + n)
+    ref = s.copy()
+    for g in c.gates:
+        ref = _dense_gate(n, g, c.params) @ ref
+    assert np.max(np.abs(O.run(c, state=s) - ref)) < 1e-13

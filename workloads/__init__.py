@@ -278,6 +278,45 @@ def mixed_param_circuit(n: int, layers: int, seed: int) -> Circuit:
                    f"mixed_param_n{n}_l{layers}")
 
 
+def trotter_tfxy(n: int, steps: int, seed: int) -> Circuit:
+    """Trotter time-evolution circuit of a 1D nearest-neighbour TFXY chain,
+    with the structure of the paper's Hamiltonian-simulation benchmark:
+    per step an RZ on every qubit, then on each even pair (q, q+1) the block
+    CNOT(q, q+1) . (RX on q, RZ on q+1) . CNOT(q, q+1), an RZ on every qubit,
+    the same blocks on the odd pairs; after the last step an RZ on every
+    qubit the odd blocks touch.  The paper gives neither the angles nor the
+    number of steps: angles are drawn uniform in [0, 2 pi) (one parameter per
+    rotation).  No observable."""
+    if n < 2:
+        raise ValueError("trotter_tfxy needs n >= 2")
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = []
+    params: List[float] = []
+
+    def rot(q: int, axis: str):
+        gates.append(grot(q, axis, len(params)))
+        params.append(rng.uniform(0.0, 2.0 * np.pi))
+
+    def blocks(first: int):
+        for q in range(first, n - 1, 2):
+            gates.append(cnot(q, q + 1))
+            rot(q, "X")
+            rot(q + 1, "Z")
+            gates.append(cnot(q, q + 1))
+
+    for _ in range(steps):
+        for q in range(n):
+            rot(q, "Z")
+        blocks(0)
+        for q in range(n):
+            rot(q, "Z")
+        blocks(1)
+    for q in range(1, 2 * ((n - 1) // 2) + 1):
+        rot(q, "Z")
+    return Circuit(n, gates, np.asarray(params, dtype=np.float64), [],
+                   f"trotter_tfxy_n{n}_s{steps}")
+
+
 def qft(n: int) -> Circuit:
     """QFT circuit as printed in Fig. 1 of the paper: for each i, H(i) then
     controlled-phase CP(ctrl=j+i-1, tgt=i, theta=-2 pi / 2^j) for j=2..n-i;

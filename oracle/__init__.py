@@ -30,7 +30,8 @@ _KIND = {W.KIND_1Q: ORC_1Q, W.KIND_C1Q: ORC_C1Q, W.KIND_2Q: ORC_2Q, W.KIND_ROT: 
 _AXIS = {"X": 0, "Y": 1, "Z": 2}
 
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("cs", "<i4"),
-                       ("axis", "<i4"), ("param", "<i4"), ("m", "<f8", (32,))], align=True)
+                       ("axis", "<i4"), ("param", "<i4"), ("m", "<f8", (32,)),
+                       ("cmask", "<u8"), ("cvals", "<u8")], align=True)
 
 
 def build(force: bool = True) -> str:
@@ -150,6 +151,10 @@ def marshal(circ: W.Circuit) -> np.ndarray:
             g["cs"][k] = gate.ctrl_state
             m = _mat(gate.matrix)
             g["m"][k][: m.size] = m
+        for q, v in zip(gate.controls, gate.control_states):
+            g["cmask"][k] |= np.uint64(1 << int(q))
+            if v:
+                g["cvals"][k] |= np.uint64(1 << int(q))
     return g
 
 

@@ -49,6 +49,8 @@ typedef struct {
     int32_t axis;        /* rot: 0 = X, 1 = Y, 2 = Z */
     int32_t param;       /* rot: index into params */
     double m[32];        /* row-major (re, im) pairs: 2x2 uses 8, 4x4 uses 32 */
+    uint64_t cmask;      /* extra control qubits (bit q = qubit q), 0 = none    */
+    uint64_t cvals;      /* the values they must hold (bit q), within cmask     */
 } orc_gate;
 
 /* ------------------------------------------------------------ Definition 1 */
@@ -166,6 +168,27 @@ static void adjoint4(const double* u, double* ud) {
         }
 }
 
+/* Extra controls (Sec. 2.4, Fig. 5: a multi-controlled gate acts only where
+ * every control qubit holds its value):
+ *     P_c (x) U + (I - P_c) (x) I,   P_c = prod_{q in cmask} |v_q><v_q|_q.
+ * Entry by entry: out[x] is the gate's result where x satisfies the
+ * controls, and in[x] elsewhere.  The gate's own entries only combine
+ * amplitudes that differ in its own qubits, so a satisfied x only reads
+ * amplitudes that satisfy the controls too. */
+static int controls_hold(int n, uint64_t x, uint64_t cmask, uint64_t cvals) {
+    for (int q = 0; q < n; ++q)
+        if (((cmask >> q) & 1u) && qbit(x, n, q) != (int)((cvals >> q) & 1u)) return 0;
+    return 1;
+}
+static void keep_unselected(int n, const double* in_, double* out_, uint64_t cmask, uint64_t cvals) {
+    const cplx* in = (const cplx*)in_;
+    cplx* out = (cplx*)out_;
+    const uint64_t N = (uint64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t xi = 0; xi < (int64_t)N; ++xi)
+        if (!controls_hold(n, (uint64_t)xi, cmask, cvals)) out[xi] = in[xi];
+}
+
 /* Apply gate g (or its adjoint) from in to out. */
 static void apply_gate(int n, const double* in, double* out, const orc_gate* g,
                        const double* params, int dagger) {
@@ -188,6 +211,7 @@ static void apply_gate(int n, const double* in, double* out, const orc_gate* g,
         orc_apply_1q(n, in, out, g->q0, u);
         break;
     }
+    if (g->cmask) keep_unselected(n, in, out, g->cmask, g->cvals);
 }
 
 /* Run gates [0, ng) on state (in place from the caller's view); work is a

@@ -562,3 +562,77 @@ def test_trotter_circuit_vs_dense(n, steps):
     for g in c.gates:
         ref = _dense_gate(n, g, c.params) @ ref
     assert np.max(np.abs(O.run(c, state=s) - ref)) < 1e-13
+
+
+# ------------------------------------------ multi-controlled gates (Sec. 2.4)
+def _dense_controlled(n, controls, states, op):
+    """P_c op + (I - P_c) with P_c the kron product of |v_q><v_q| on the
+    control qubits (identity elsewhere)."""
+    proj = [np.diag([1.0, 0.0]).astype(np.complex128), np.diag([0.0, 1.0]).astype(np.complex128)]
+    f = [np.eye(2, dtype=np.complex128)] * n
+    f = list(f)
+    for c, v in zip(controls, states):
+        f[c] = proj[v]
+    P = kron_all(*f)
+    return P @ op + (np.eye(2 ** n) - P)
+
+
+def test_fig5_doubly_controlled_values():
+    """Fig. 5: a doubly-controlled 1q gate on 3 qubits (controls q0 = q1 = 1,
+    target q2) changes only the printed pair {6}, {7}, and that pair is U
+    applied to (phi_6, phi_7)."""
+    g = _gold("fig5_cc1q_n3.json")
+    n = g["n"]
+    rng = np.random.default_rng(70)
+    u = W.haar_unitary(2, rng)
+    phi = _rand_state(n, 71)
+    c = W.Circuit(n, [W.with_controls(W.g1(g["target"], u), g["controls"])])
+    out = O.run(c, state=phi)
+    a, b = g["a"][0], g["b"][0]
+    untouched = [x for x in range(2 ** n) if x not in (a, b)]
+    assert np.array_equal(out[untouched], phi[untouched])
+    assert np.max(np.abs(out[[a, b]] - u @ phi[[a, b]])) < 1e-15
+
+
+@pytest.mark.parametrize("n", [3, 5, 6])
+def test_controlled_gates_vs_dense_projector(n):
+    """Extra controls on 1q, controlled-1q and 2q gates, any positions and
+    control states, against the dense projector form built with kron."""
+    rng = np.random.default_rng(72 + n)
+    for trial in range(12):
+        k = int(rng.integers(1, 3))             # gate qubits (1 or 2)
+        nc = int(rng.integers(1, n - k + 1))    # extra controls
+        qs = [int(x) for x in rng.choice(n, size=k + nc, replace=False)]
+        tgt, ctrl = qs[:k], qs[k:]
+        st = [int(x) for x in rng.integers(0, 2, size=nc)]
+        phi = _rand_state(n, 80 + 10 * n + trial)
+        if k == 1:
+            u = W.haar_unitary(2, rng)
+            gate, op = W.g1(tgt[0], u), dense_1q(n, tgt[0], u)
+        elif trial % 2:
+            u = W.haar_unitary(2, rng)
+            cs = int(rng.integers(2))
+            gate, op = W.gc(tgt[0], tgt[1], u, cs), dense_c1q(n, tgt[0], tgt[1], u, cs)
+        else:
+            u = W.haar_unitary(4, rng)
+            gate, op = W.g2(tgt[0], tgt[1], u), dense_2q(n, tgt[0], tgt[1], u)
+        c = W.Circuit(n, [W.with_controls(gate, ctrl, st)])
+        ref = _dense_controlled(n, ctrl, st, op) @ phi
+        assert np.max(np.abs(O.run(c, state=phi) - ref)) < 1e-14, (trial, qs, st)
+
+
+def test_toffoli_truth_table_and_single_control():
+    """The Toffoli gate permutes |110> and |111> (qubits c0, c1, t) and fixes
+    every other basis state; one extra control on a 1q gate is the controlled
+    gate of Sec. 2.2."""
+    n = 3
+    for x in range(8):
+        out = O.run(W.Circuit(n, [W.toffoli(0, 1, 2)]), state=O.basis(n, x))
+        y = x ^ 1 if (x >> 1) == 3 else x
+        assert np.array_equal(out, O.basis(n, y))
+    rng = np.random.default_rng(74)
+    u = W.haar_unitary(2, rng)
+    phi = _rand_state(5, 75)
+    for cs in (0, 1):
+        a = O.run(W.Circuit(5, [W.with_controls(W.g1(4, u), (1,), (cs,))]), state=phi)
+        assert np.array_equal(a, O.apply_c1q(phi, 1, 4, u, cs))

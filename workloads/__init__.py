@@ -26,6 +26,7 @@ matrix with the phases of ``diag(R)`` divided out).  Random numbers come from
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -46,6 +47,10 @@ class Gate:
     ctrl_state: int = 1                   # c1q only
     axis: Optional[str] = None            # rot only
     param: int = -1                       # rot only: index into params
+    # extra controls (Sec. 2.4): the gate acts only where each qubit in
+    # `controls` holds the matching value in `control_states`
+    controls: Tuple[int, ...] = ()
+    control_states: Tuple[int, ...] = ()
 
 
 @dataclass
@@ -101,6 +106,22 @@ def g2(qa: int, qb: int, u: np.ndarray) -> Gate:
 def grot(q: int, axis: str, param: int) -> Gate:
     assert axis in AXES
     return Gate(KIND_ROT, (int(q),), None, 1, axis, int(param))
+
+
+def with_controls(gate: Gate, controls: Sequence[int], states: Optional[Sequence[int]] = None) -> Gate:
+    """The gate with extra control qubits (states default to 1): it then acts
+    only where every one of them holds its state (a multi-controlled gate,
+    Sec. 2.4)."""
+    states = [1] * len(controls) if states is None else list(states)
+    if len(states) != len(controls):
+        raise ValueError("one state per control")
+    return dataclasses.replace(gate, controls=tuple(int(c) for c in controls),
+                               control_states=tuple(int(v) for v in states))
+
+
+def toffoli(c0: int, c1: int, t: int) -> Gate:
+    """Doubly-controlled X (Sec. 2.4): X on t where c0 = c1 = 1."""
+    return with_controls(g1(t, X), (c0, c1))
 
 
 def cnot(qc: int, qt: int) -> Gate:
@@ -340,7 +361,7 @@ def inverse(c: Circuit) -> Circuit:
         if g.kind == KIND_ROT:
             gates.append(g)
         else:
-            gates.append(Gate(g.kind, g.qubits, g.matrix.conj().T.copy(), g.ctrl_state))
+            gates.append(dataclasses.replace(g, matrix=g.matrix.conj().T.copy()))
     return Circuit(c.n, gates, np.asarray(params, dtype=np.float64), [], c.name + "_inv")
 
 

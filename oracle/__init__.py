@@ -60,6 +60,7 @@ def lib():
         L.orc_apply_1q.argtypes = [i, vp, vp, i, vp]
         L.orc_apply_c1q.argtypes = [i, vp, vp, i, i, i, vp]
         L.orc_apply_2q.argtypes = [i, vp, vp, i, i, vp]
+        L.orc_apply_kq.argtypes = [i, vp, vp, i, vp, vp]
         L.orc_rotation.argtypes = [i, d, vp]
         L.orc_run.argtypes = [i, vp, vp, i64, vp, vp]
         L.orc_init_basis.argtypes = [i, vp, u64]
@@ -125,6 +126,16 @@ def apply_2q(state: np.ndarray, qa: int, qb: int, u: np.ndarray) -> np.ndarray:
     n = int(np.log2(s.size))
     out = np.empty_like(s)
     lib().orc_apply_2q(n, _p(s), _p(out), qa, qb, _p(_mat(u)))
+    return out
+
+
+def apply_kq(state: np.ndarray, qubits: Sequence[int], u: np.ndarray) -> np.ndarray:
+    """A 2^k x 2^k gate on `qubits` (qubits[0] = most significant local bit)."""
+    s = _c128(state)
+    n = int(np.log2(s.size))
+    qs = np.ascontiguousarray(list(qubits), dtype=np.int32)
+    out = np.empty_like(s)
+    lib().orc_apply_kq(n, _p(s), _p(out), int(qs.size), _p(qs), _p(_mat(u)))
     return out
 
 

@@ -133,6 +133,30 @@ void orc_apply_2q(int n, const double* in_, double* out_, int qa, int qb, const 
     }
 }
 
+/* psi = U_{(qs[0], .., qs[k-1])} phi for a 2^k x 2^k U (Sec. 2.4: a gate on
+ * any k qubits, contiguous or not), entry by entry.  Row/column index
+ * sum_i x_{qs[i]} 2^(k-1-i): qs[0] is the most significant local bit, which
+ * is eq. (1)'s order when the qubits are contiguous and ascending. */
+void orc_apply_kq(int n, const double* in_, double* out_, int k, const int* qs, const double* u) {
+    const cplx* in = (const cplx*)in_;
+    cplx* out = (cplx*)out_;
+    const uint64_t N = (uint64_t)1 << n;
+    const int dim = 1 << k;
+#pragma omp parallel for schedule(static)
+    for (int64_t xi = 0; xi < (int64_t)N; ++xi) {
+        uint64_t x = (uint64_t)xi;
+        int r = 0;
+        for (int i = 0; i < k; ++i) r |= qbit(x, n, qs[i]) << (k - 1 - i);
+        cplx acc = 0;
+        for (int c = 0; c < dim; ++c) {
+            uint64_t y = x;
+            for (int i = 0; i < k; ++i) y = qforce(y, n, qs[i], (c >> (k - 1 - i)) & 1);
+            acc += mat(u, dim, r, c) * in[y];
+        }
+        out[x] = acc;
+    }
+}
+
 /* the Pauli matrices, row-major (re, im) pairs */
 static const double PAULI[3][8] = {
     {0, 0, 1, 0, 1, 0, 0, 0},     /* X = [[0,1],[1,0]] */

@@ -636,3 +636,70 @@ def test_toffoli_truth_table_and_single_control():
     for cs in (0, 1):
         a = O.run(W.Circuit(5, [W.with_controls(W.g1(4, u), (1,), (cs,))]), state=phi)
         assert np.array_equal(a, O.apply_c1q(phi, 1, 4, u, cs))
+
+
+# ------------------------------------------------ k-qubit gates (Sec. 2.4)
+def _haar(d, rng):
+    return W.haar_unitary(d, rng)
+
+
+def test_kq_on_every_qubit_is_plain_matvec():
+    """k = n on qubits (0, .., n-1): the local index is the whole index, so
+    the gate is U @ phi."""
+    rng = np.random.default_rng(301)
+    for n in (1, 2, 3, 4):
+        u = _haar(2 ** n, rng)
+        phi = W.random_state(n, 302 + n)
+        np.testing.assert_allclose(O.apply_kq(phi, list(range(n)), u), u @ phi, atol=1e-14)
+
+
+def test_kq_permuted_qubits_is_axis_transpose():
+    """k = n on a permutation of the qubits: U acts on the state tensor with
+    its axes in that order (numpy transpose, then matvec, then back)."""
+    rng = np.random.default_rng(311)
+    n = 4
+    for _ in range(5):
+        perm = [int(x) for x in rng.permutation(n)]
+        u = _haar(2 ** n, rng)
+        phi = W.random_state(n, int(rng.integers(1 << 30)))
+        t = phi.reshape((2,) * n).transpose(perm).reshape(-1)
+        want = (u @ t).reshape((2,) * n).transpose(np.argsort(perm)).reshape(-1)
+        np.testing.assert_allclose(O.apply_kq(phi, perm, u), want, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_kq_contiguous_is_kron(k):
+    """Contiguous ascending qubits (q, .., q+k-1): eq. (1), (I (x) U (x) I) phi."""
+    rng = np.random.default_rng(320 + k)
+    n = 6
+    for q in range(n - k + 1):
+        u = _haar(2 ** k, rng)
+        phi = W.random_state(n, 330 + q)
+        m = np.kron(np.kron(np.eye(2 ** q), u), np.eye(2 ** (n - q - k)))
+        np.testing.assert_allclose(O.apply_kq(phi, list(range(q, q + k)), u), m @ phi, atol=1e-14)
+
+
+def test_kq_product_gate_equals_single_qubit_gates():
+    """U = A (x) B (x) C on non-contiguous qubits (a, b, c) in that order is A
+    on a, B on b and C on c."""
+    rng = np.random.default_rng(341)
+    n = 7
+    for _ in range(4):
+        a, b, c = (int(x) for x in rng.choice(n, size=3, replace=False))
+        A, B, C = _haar(2, rng), _haar(2, rng), _haar(2, rng)
+        phi = W.random_state(n, int(rng.integers(1 << 30)))
+        want = O.apply_1q(O.apply_1q(O.apply_1q(phi, a, A), b, B), c, C)
+        np.testing.assert_allclose(O.apply_kq(phi, [a, b, c], np.kron(np.kron(A, B), C)), want,
+                                   atol=1e-14)
+
+
+def test_kq_toffoli_matrix_equals_doubly_controlled_x():
+    """The 8 x 8 Toffoli permutation on (c0, c1, t) equals X on t with two
+    extra controls (the multi-controlled form of the same gate)."""
+    n = 5
+    tof = np.eye(8, dtype=complex)
+    tof[[6, 7]] = tof[[7, 6]]
+    phi = W.random_state(n, 351)
+    for c0, c1, t in [(0, 1, 2), (4, 0, 2), (3, 1, 0)]:
+        want = O.run(W.Circuit(n, [W.toffoli(c0, c1, t)]), phi)
+        np.testing.assert_allclose(O.apply_kq(phi, [c0, c1, t], tof), want, atol=1e-15)

@@ -89,7 +89,15 @@ typedef struct qsv_state_s* qsv_state;
  *   QSV_G1Q : q0 = target, m[0..7]
  *   QSV_GC1Q: q0 = control, q1 = target, ctrl_state in {0,1}, m[0..7]
  *   QSV_G2Q : (q0, q1) = (qa, qb), m[0..31]
- *   QSV_GROT: q0 = target, axis, param (index into the params array)      */
+ *   QSV_GROT: q0 = target, axis, param (index into the params array)
+ * Extra controls (Sec. 2.4, Fig. 5), any kind: cmask (bit q = qubit q) names
+ * further control qubits, disjoint from the gate's own qubits, and cvals
+ * (a subset of cmask) the values they must hold.  The gate then applies
+ *     P (x) G + (I - P) (x) I,   P = prod_{q in cmask} |v_q><v_q|_q,
+ * i.e. G acts only on the amplitudes whose control bits all hold their
+ * values (a Toffoli is X on q0 with two extra controls).  cmask = 0: none.
+ * Such gates are not fused (each is its own pass over the amplitudes it
+ * changes); qsv_batch_run and the rotations of qsv_adjoint reject them. */
 typedef struct {
     int32_t kind;
     int32_t q0, q1;
@@ -97,6 +105,8 @@ typedef struct {
     int32_t axis;
     int32_t param;
     double m[32];
+    uint64_t cmask;
+    uint64_t cvals;
 } qsv_gate;
 
 /* Per-kernel timing collected while profiling is on (see qsv_profile_*). */
@@ -161,6 +171,25 @@ qsv_status qsv_applyC1q(qsv_state st, int qc, int qt, int ctrl_state, const doub
  * not): each quad of indices that differ only in the bits of qa and qb is
  * multiplied by U, whose row/column index is 2*x_qa + x_qb.  u: 32 doubles. */
 qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u);
+
+/* Multi-controlled 1-qubit gate (Sec. 2.4, Fig. 5): U acts on target qt on
+ * the amplitudes whose controls[i] bits all equal ctrl_states[i] (each 0 or
+ * 1; ctrl_states may be NULL for all 1), the rest is untouched.  The pairs
+ * it updates come from zero-bit insertion at the nctrl + 1 positions of the
+ * controls and the target (Algs. 1-2 generalised), so each control halves
+ * the amplitudes read and written.  0 <= nctrl <= n - 1, qubits distinct and
+ * in [0, n).  u: 8 doubles. */
+qsv_status qsv_applyMC1q(qsv_state st, int nctrl, const int* controls, const int* ctrl_states,
+                         int qt, const double* u);
+
+/* General k-qubit gate on any k distinct qubits, contiguous or not (Sec.
+ * 2.4: the masks of Algs. 1-3 extended by one inserted zero bit per extra
+ * qubit).  U is 2^k x 2^k, row-major (re, im) pairs (2 * 4^k doubles),
+ * rows/columns indexed by sum_i x_{qubits[i]} 2^(k-1-i): qubits[0] is the
+ * most significant bit of the local index, which is eq. (1)'s order when
+ * the qubits are contiguous and ascending.  1 <= k <= 5, k <= n.  The matrix
+ * is copied to device memory before the call returns. */
+qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u);
 
 /* Apply gates g[0..ng) in order.  Rotations read params[0..nparams).  By
  * default gates are grouped into fused passes: each pass loads a tile of

@@ -317,6 +317,7 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             };
             const bool two = G.kind == QSV_GC1Q || G.kind == QSV_G2Q;
             if (G.kind < QSV_G1Q || G.kind > QSV_GROT) return err("unknown kind");
+            if (G.cmask || G.cvals) return err("extra controls are not supported in a batch");
             if (G.q0 < 0 || G.q0 >= n || (two && (G.q1 < 0 || G.q1 >= n || G.q1 == G.q0)))
                 return err("bad qubit");
             mix(h, uint64_t(G.kind) | (uint64_t(G.q0) << 8) | (uint64_t(two ? G.q1 : 0) << 16) |

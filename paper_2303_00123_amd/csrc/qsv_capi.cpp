@@ -118,6 +118,19 @@ qsv_status lower(qsv_ctx ctx, int n, const qsv_gate* g, int64_t ng, const double
         default:
             return fail(ctx, QSV_ERR_ARG, at + "unknown gate kind");
         }
+        // extra controls (Sec. 2.4): qubits distinct from the gate's own
+        if (G.cmask || G.cvals) {
+            if (G.cvals & ~G.cmask) return fail(ctx, QSV_ERR_ARG, at + "cvals names a qubit outside cmask");
+            if (n < 64 && (G.cmask >> n)) return fail(ctx, QSV_ERR_QUBIT, at + "control qubit out of range");
+            uint64_t own = uint64_t(1) << G.q0;
+            if (G.kind == QSV_GC1Q || G.kind == QSV_G2Q) own |= uint64_t(1) << G.q1;
+            if (G.cmask & own) return fail(ctx, QSV_ERR_QUBIT, at + "control qubit is one of the gate's qubits");
+            for (int q = 0; q < n; ++q)
+                if ((G.cmask >> q) & 1) {
+                    p.cm |= uint64_t(1) << pos_of(n, q);
+                    if ((G.cvals >> q) & 1) p.cv |= uint64_t(1) << pos_of(n, q);
+                }
+        }
         if (dagger) {  // conjugate transpose
             const int d = p.kind == QSV_G2Q ? 4 : 2;
             double t[32];
@@ -501,13 +514,82 @@ qsv_status qsv_apply2q(qsv_state st, int qa, int qb, const double* u) {
     }
 }
 
+qsv_status qsv_applyMC1q(qsv_state st, int nctrl, const int* controls, const int* ctrl_states,
+                         int qt, const double* u) {
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        const int n = st->n;
+        if (!u) return fail(ctx, QSV_ERR_ARG, "null matrix");
+        if (nctrl < 0 || nctrl > n - 1 || (nctrl > 0 && !controls))
+            return fail(ctx, QSV_ERR_ARG, "need 0 <= nctrl <= n - 1 and a control array");
+        if (qt < 0 || qt >= n) return fail(ctx, QSV_ERR_QUBIT, "target out of range");
+        PGate p{};
+        p.kind = QSV_G1Q;
+        p.p0 = pos_of(n, qt);
+        std::memcpy(p.m, u, 8 * sizeof(double));
+        uint64_t seen = uint64_t(1) << qt;
+        for (int i = 0; i < nctrl; ++i) {
+            const int q = controls[i];
+            if (q < 0 || q >= n) return fail(ctx, QSV_ERR_QUBIT, "control out of range");
+            if ((seen >> q) & 1) return fail(ctx, QSV_ERR_QUBIT, "repeated qubit");
+            seen |= uint64_t(1) << q;
+            const int v = ctrl_states ? ctrl_states[i] : 1;
+            if (v != 0 && v != 1) return fail(ctx, QSV_ERR_ARG, "control state must be 0 or 1");
+            p.cm |= uint64_t(1) << pos_of(n, q);
+            if (v) p.cv |= uint64_t(1) << pos_of(n, q);
+        }
+        HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, n, st->dtype, p), "applyMC1q");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
+}
+
+qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u) {
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        const int n = st->n;
+        if (!u || !qubits) return fail(ctx, QSV_ERR_ARG, "null matrix or qubit array");
+        if (k < 1 || k > 5 || k > n) return fail(ctx, QSV_ERR_ARG, "need 1 <= k <= 5 and k <= n");
+        int pos[5];
+        uint64_t seen = 0;
+        for (int i = 0; i < k; ++i) {
+            if (qubits[i] < 0 || qubits[i] >= n) return fail(ctx, QSV_ERR_QUBIT, "qubit out of range");
+            if ((seen >> qubits[i]) & 1) return fail(ctx, QSV_ERR_QUBIT, "repeated qubit");
+            seen |= uint64_t(1) << qubits[i];
+            pos[i] = pos_of(n, qubits[i]);
+        }
+        // the matrix in the state's real type, through the plan staging buffer
+        const size_t vals = size_t(2) << (2 * k);
+        const size_t rs = st->dtype == QSV_C128 ? sizeof(double) : sizeof(float);
+        void* host = nullptr;
+        HIP_OR_FAIL(ctx, plan_staging(ctx, vals * rs, &host), "applyKq staging");
+        for (size_t i = 0; i < vals; ++i) {
+            if (st->dtype == QSV_C128) static_cast<double*>(host)[i] = u[i];
+            else static_cast<float*>(host)[i] = float(u[i]);
+        }
+        void* dev = nullptr;
+        HIP_OR_FAIL(ctx, plan_upload(ctx, vals * rs, &dev), "applyKq upload");
+        HIP_OR_FAIL(ctx, launch_kq(ctx, st->ptr, n, st->dtype, k, pos, dev), "applyKq");
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
+}
+
 static bool same_gates(const std::vector<PGate>& a, const std::vector<PGate>& b) {
     if (a.size() != b.size()) return false;
     for (size_t i = 0; i < a.size(); ++i) {
         const PGate& x = a[i];
         const PGate& y = b[i];
         if (x.kind != y.kind || x.p0 != y.p0 || x.p1 != y.p1 || x.cs != y.cs || x.tag != y.tag ||
-            std::memcmp(x.m, y.m, sizeof(x.m)) != 0)
+            x.cm != y.cm || x.cv != y.cv || std::memcmp(x.m, y.m, sizeof(x.m)) != 0)
             return false;
     }
     return true;
@@ -742,6 +824,10 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
         if (qsv_status s = lower(ctx, n, g, ng, params, nparams, fwd)) return s;
         std::vector<int> rot_param(size_t(ng), -1), rot_axis(size_t(ng), -1);
         for (int64_t i = 0; i < ng; ++i)
+            if (g[i].kind == QSV_GROT && g[i].cmask)
+                return fail(ctx, QSV_ERR_ARG,
+                            "gate " + std::to_string(i) + ": a rotation with extra controls has no adjoint gradient here");
+        for (int64_t i = 0; i < ng; ++i)
             if (g[i].kind == QSV_GROT) {
                 rot_param[size_t(i)] = g[i].param;
                 rot_axis[size_t(i)] = g[i].axis;
@@ -908,6 +994,11 @@ qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const
                 o.ctrl_state = x.cs;
                 o.param = -1;
                 std::memcpy(o.m, x.m, sizeof(o.m));
+                for (int p = 0; p < n; ++p)
+                    if ((x.cm >> p) & 1) {
+                        o.cmask |= uint64_t(1) << pos_of(n, p);
+                        if ((x.cv >> p) & 1) o.cvals |= uint64_t(1) << pos_of(n, p);
+                    }
                 if (out) out[k] = o;
                 if (pass_of_out) pass_of_out[k] = p;
             }

@@ -279,6 +279,88 @@ __global__ __launch_bounds__(kThreads) void k_perm2q(typename V2T<R>::type* __re
     }
 }
 
+// ------------------------------------------- multi-controlled gates (Sec. 2.4)
+// A gate with extra controls changes only the amplitudes whose control bits
+// hold their values.  Item j names the first amplitude of one pair (NB = 1)
+// or quad (NB = 2): j with a zero bit inserted at each of the npos positions
+// of the controls and the gate's own bits (ascending, so each insertion
+// leaves the lower ones in place -- Alg. 2's two insertions generalised),
+// then the control values `fix` set.  Each control halves the items.
+struct InsPos { int32_t p[kMaxQubits]; };
+
+template <typename R, int NB, int PK = PK_DENSE>
+__global__ __launch_bounds__(kThreads) void k_mc(typename V2T<R>::type* __restrict__ s,
+                                                 uint64_t items, int npos, InsPos ip, uint64_t fix,
+                                                 int pa, int pb, M4<R> u) {
+    using V = typename V2T<R>::type;
+    const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
+    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < items;
+         j += uint64_t(gridDim.x) * kThreads) {
+        uint64_t x = j;
+        for (int i = 0; i < npos; ++i) x = insert0(x, ip.p[i]);
+        x |= fix;
+        if constexpr (NB == 1) {
+            const V a = ld_nt(s + x), b = ld_nt(s + x + wa);
+            V oa, ob;
+            pair_op<R, PK>(u.v, a, b, oa, ob);
+            st_nt(s + x, oa);
+            st_nt(s + x + wa, ob);
+        } else {
+            // local index 2 * x_a + x_b (eq. (1) order of the 2-qubit gate)
+            V in[4], out[4];
+            in[0] = ld_nt(s + x);
+            in[1] = ld_nt(s + x + wb);
+            in[2] = ld_nt(s + x + wa);
+            in[3] = ld_nt(s + x + wa + wb);
+            mv4(u.v, in, out);
+            st_nt(s + x, out[0]);
+            st_nt(s + x + wb, out[1]);
+            st_nt(s + x + wa, out[2]);
+            st_nt(s + x + wa + wb, out[3]);
+        }
+    }
+}
+
+// ----------------------------------------- general k-qubit gate (Sec. 2.4)
+// Item j: zero bits inserted at the k gate positions (ascending); slot c of
+// the item is the amplitude at x + off[c], where off[c] spells the local
+// index c over the gate's qubits in the caller's order.  Each thread loads
+// its 2^K amplitudes, then forms and stores one output row at a time
+// (row r = sum_c U[r][c] v[c]), so only the inputs stay in registers.  U
+// sits in device memory and is read with uniform (scalar) loads.
+template <int K>
+struct KOff { uint64_t o[1 << K]; };
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_kq(typename V2T<R>::type* __restrict__ s,
+                                                 uint64_t items, InsPos ip, KOff<K> off,
+                                                 const R* __restrict__ u) {
+    using V = typename V2T<R>::type;
+    constexpr int D = 1 << K;
+    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < items;
+         j += uint64_t(gridDim.x) * kThreads) {
+        uint64_t x = j;
+#pragma unroll
+        for (int i = 0; i < K; ++i) x = insert0(x, ip.p[i]);
+        V v[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = ld_nt(s + x + off.o[c]);
+        // rows one at a time (not unrolled): the row index is uniform, so
+        // the matrix row and the output offset come from scalar loads
+#pragma unroll 1
+        for (int r = 0; r < D; ++r) {
+            R re, im;
+            cmac_first(u[2 * D * r], u[2 * D * r + 1], v[0], re, im);
+#pragma unroll
+            for (int c = 1; c < D; ++c) cmac(u[2 * (D * r + c)], u[2 * (D * r + c) + 1], v[c], re, im);
+            V o;
+            o.x = re;
+            o.y = im;
+            st_nt(s + x + off.o[r], o);
+        }
+    }
+}
+
 template <typename R>
 unsigned grid_for(uint64_t items, int per_thread) {
     const uint64_t per_block = uint64_t(kThreads) * per_thread;
@@ -484,6 +566,86 @@ hipError_t apply2q_t(qsv_ctx ctx, void* s, int n, int pa, int pb, const double* 
     return hipGetLastError();
 }
 
+// A gate with extra controls (PGate::cm / cv): a controlled 1q gate's own
+// control joins them, so the base is U on one target or a 2-qubit U.
+template <typename R>
+hipError_t mc_t(qsv_ctx ctx, void* s, int n, const PGate& g) {
+    using V = typename V2T<R>::type;
+    uint64_t cm = g.cm, cv = g.cv;
+    int nb = 1, pa = g.p0, pb = 0;
+    if (g.kind == QSV_GC1Q) {
+        cm |= uint64_t(1) << g.p0;
+        if (g.cs) cv |= uint64_t(1) << g.p0;
+        pa = g.p1;
+    } else if (g.kind == QSV_G2Q) {
+        nb = 2;
+        pb = g.p1;
+    }
+    const uint64_t ins = cm | (uint64_t(1) << pa) | (nb == 2 ? uint64_t(1) << pb : 0);
+    InsPos ip{};
+    int npos = 0;
+    for (int p = 0; p < n; ++p)
+        if ((ins >> p) & 1) ip.p[npos++] = p;
+    const uint64_t items = uint64_t(1) << (n - npos);
+    M4<R> u{};
+    for (int i = 0; i < (nb == 2 ? 32 : 8); ++i) u.v[i] = R(g.m[i]);
+    const dim3 grid(capped_grid((items + kThreads - 1) / kThreads));
+    const double bytes = 2.0 * double(items << nb) * sizeof(V);
+    if (nb == 2) {
+        prof_before(ctx, sizeof(R) == 8 ? "mc2q_c128" : "mc2q_c64", bytes);
+        hipLaunchKernelGGL((k_mc<R, 2>), grid, dim3(kThreads), 0, ctx->stream, static_cast<V*>(s), items,
+                           npos, ip, cv, pa, pb, u);
+    } else if (is_x2(g.m)) {   // Toffoli and other multi-controlled X: the pairs swap
+        prof_before(ctx, sizeof(R) == 8 ? "mcx_c128" : "mcx_c64", bytes);
+        hipLaunchKernelGGL((k_mc<R, 1, PK_SWAP>), grid, dim3(kThreads), 0, ctx->stream, static_cast<V*>(s),
+                           items, npos, ip, cv, pa, pb, u);
+    } else {
+        prof_before(ctx, sizeof(R) == 8 ? "mc1q_c128" : "mc1q_c64", bytes);
+        hipLaunchKernelGGL((k_mc<R, 1>), grid, dim3(kThreads), 0, ctx->stream, static_cast<V*>(s), items,
+                           npos, ip, cv, pa, pb, u);
+    }
+    prof_after(ctx);
+    return hipGetLastError();
+}
+
+// k-qubit gate: positions pos[i] of the caller's qubits (pos[0] = most
+// significant local bit), U already in device memory in the state's type.
+template <typename R, int K>
+hipError_t kq_launch(qsv_ctx ctx, void* s, int n, const int* pos, const void* du) {
+    using V = typename V2T<R>::type;
+    InsPos ip{};
+    int sorted[K];
+    for (int i = 0; i < K; ++i) sorted[i] = pos[i];
+    for (int i = 1; i < K; ++i)
+        for (int j = i; j > 0 && sorted[j - 1] > sorted[j]; --j) std::swap(sorted[j - 1], sorted[j]);
+    for (int i = 0; i < K; ++i) ip.p[i] = sorted[i];
+    KOff<K> off{};
+    for (int c = 0; c < (1 << K); ++c) {
+        uint64_t o = 0;
+        for (int i = 0; i < K; ++i)
+            if ((c >> (K - 1 - i)) & 1) o |= uint64_t(1) << pos[i];
+        off.o[c] = o;
+    }
+    const uint64_t items = uint64_t(1) << (n - K);
+    prof_before(ctx, sizeof(R) == 8 ? "kq_c128" : "kq_c64", 2.0 * double(uint64_t(1) << n) * sizeof(V));
+    hipLaunchKernelGGL((k_kq<R, K>), dim3(capped_grid((items + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       ctx->stream, static_cast<V*>(s), items, ip, off, static_cast<const R*>(du));
+    prof_after(ctx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t kq_t(qsv_ctx ctx, void* s, int n, int k, const int* pos, const void* du) {
+    switch (k) {
+    case 1: return kq_launch<R, 1>(ctx, s, n, pos, du);
+    case 2: return kq_launch<R, 2>(ctx, s, n, pos, du);
+    case 3: return kq_launch<R, 3>(ctx, s, n, pos, du);
+    case 4: return kq_launch<R, 4>(ctx, s, n, pos, du);
+    case 5: return kq_launch<R, 5>(ctx, s, n, pos, du);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_init_basis(qsv_ctx ctx, void* s, int n, int dtype, uint64_t b) {
@@ -501,7 +663,11 @@ hipError_t launch_apply2q(qsv_ctx ctx, void* s, int n, int dtype, int pa, int pb
     return dtype == QSV_C128 ? apply2q_t<double>(ctx, s, n, pa, pb, u)
                              : apply2q_t<float>(ctx, s, n, pa, pb, u);
 }
+hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du) {
+    return dtype == QSV_C128 ? kq_t<double>(ctx, s, n, k, pos, du) : kq_t<float>(ctx, s, n, k, pos, du);
+}
 hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g) {
+    if (g.cm) return dtype == QSV_C128 ? mc_t<double>(ctx, s, n, g) : mc_t<float>(ctx, s, n, g);
     switch (g.kind) {
     case QSV_G1Q: return launch_apply1q(ctx, s, n, dtype, g.p0, g.m);
     case QSV_GC1Q: return launch_applyc1q(ctx, s, n, dtype, g.p0, g.p1, g.cs, g.m);

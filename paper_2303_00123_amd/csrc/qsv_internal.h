@@ -27,6 +27,10 @@ struct PGate {
     int cs;
     double m[32];
     int tag = -1;   // adjoint sweep: index of the forward gate a KROT rewinds
+    // extra controls (Sec. 2.4) as index-bit masks: the gate acts where the
+    // bits in cm equal those of cv.  Such a gate is never fused: it runs as
+    // its own pass (k_mc) and orders every gate around it.
+    uint64_t cm = 0, cv = 0;
 };
 
 // Internal kind for the adjoint sweep: a rotation exp(-i theta P/2) being
@@ -278,6 +282,10 @@ hipError_t launch_applyc1q(qsv_ctx ctx, void* s, int n, int dtype, int pc, int p
                            const double* u);
 hipError_t launch_apply2q(qsv_ctx ctx, void* s, int n, int dtype, int pa, int pb, const double* u);
 hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g);
+// k-qubit gate (1 <= k <= 5) on index-bit positions pos[0..k) (pos[0] = most
+// significant local bit); du: the 2^k x 2^k matrix in device memory, in the
+// state's real type.
+hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du);
 
 // Largest tile (log2 amplitudes) the tile kernel supports for a dtype.
 int tile_bits_max(int dtype);

@@ -27,7 +27,14 @@
 
 namespace qsv {
 
-static inline uint64_t gate_mask(const PGate& g) {
+// A gate with extra controls is a barrier: its mask covers every position
+// plus bit 63, which no tile set ever holds (positions are < 36), so no
+// pass can take it, even one whose tile spans the whole state, and no later
+// gate can overtake it; the planner gives it a pass of its own when it
+// reaches the front.
+constexpr uint64_t kBarrierBit = uint64_t(1) << 63;
+static inline uint64_t gate_mask(const PGate& g, int n) {
+    if (g.cm) return ((uint64_t(1) << n) - 1) | kBarrierBit;
     uint64_t m = uint64_t(1) << g.p0;
     if (!is_1q(g.kind)) m |= uint64_t(1) << g.p1;
     return m;
@@ -337,7 +344,7 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
         if (!has[p]) return;
         has[p] = false;
         const int l = last[p];
-        if (l >= 0 && out[size_t(l)].kind == QSV_G1Q) {
+        if (l >= 0 && out[size_t(l)].kind == QSV_G1Q && !out[size_t(l)].cm) {
             PGate& o = out[size_t(l)];
             cd u[4];
             m2_from(o.m, u);
@@ -348,7 +355,7 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
             }
             return;
         }
-        if (l >= 0 && out[size_t(l)].kind == QSV_G2Q) {
+        if (l >= 0 && out[size_t(l)].kind == QSV_G2Q && !out[size_t(l)].cm) {
             PGate& o = out[size_t(l)];
             static const cd I2[4] = {1, 0, 0, 1};
             const M4 L = o.p0 == p ? kron(pend[p], I2) : kron(I2, pend[p]);
@@ -369,6 +376,18 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
 
     for (int gi : idx) {
         const PGate& g = gates[size_t(gi)];
+        if (g.cm) {
+            // extra controls: pending products on its qubits and controls go
+            // first, the gate stays whole, and nothing folds into it later
+            uint64_t own = g.cm | (uint64_t(1) << g.p0);
+            if (!is_1q(g.kind)) own |= uint64_t(1) << g.p1;
+            for (int p = 0; p < 64; ++p)
+                if ((own >> p) & 1) flush(p);
+            out.push_back(g);
+            for (int p = 0; p < 64; ++p)
+                if ((own >> p) & 1) last[p] = int(out.size()) - 1;
+            continue;
+        }
         if (g.kind == KROT) {
             // kept whole (its partial sum is taken at this point)
             flush(g.p0);
@@ -392,7 +411,8 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
         int prev = -1;
         if (last[a] >= 0 && last[a] == last[b]) {
             const PGate& o = out[size_t(last[a])];
-            if (!is_1q(o.kind) && o.kind != KROT && ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a)))
+            if (!is_1q(o.kind) && o.kind != KROT && !o.cm &&
+                ((o.p0 == a && o.p1 == b) || (o.p0 == b && o.p1 == a)))
                 prev = last[a];
         }
         // fuse into one dense 2q gate only where that does not add arithmetic
@@ -457,6 +477,9 @@ static int count_passes(std::vector<int> rem, const std::vector<uint64_t>& masks
         take.clear();
         defer.clear();
         greedy(rem, masks, S, K, true, take, defer);
+        if (take.empty()) {   // a barrier gate at the front: a pass of its own
+            defer.erase(defer.begin());
+        }
         rem.swap(defer);
         ++np;
     }
@@ -508,7 +531,7 @@ static uint64_t choose_bits_tail(const std::vector<int>& rem, const std::vector<
 std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {
     std::vector<Pass> passes;
     std::vector<uint64_t> masks(gates.size());
-    for (size_t i = 0; i < gates.size(); ++i) masks[i] = gate_mask(gates[i]);
+    for (size_t i = 0; i < gates.size(); ++i) masks[i] = gate_mask(gates[i], n);
     if (n < kMinTileBits || cfg.tile_bits < kMinTileBits) {
         for (size_t i = 0; i < gates.size(); ++i) {
             Pass ps;
@@ -527,6 +550,15 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
 
     while (!rem.empty()) {
+        if (gates[size_t(rem[0])].cm) {
+            Pass ps;
+            ps.single = true;
+            ps.k = K;
+            ps.gates.push_back(rem[0]);
+            passes.push_back(std::move(ps));
+            rem.erase(rem.begin());
+            continue;
+        }
         const uint64_t low = (uint64_t(1) << L) - 1;
         uint64_t S = choose_bits(rem, masks, low, K);
         if (rem.size() <= kTailLookGates) S = choose_bits_tail(rem, masks, low, K, S);
@@ -564,7 +596,8 @@ const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>&
     for (size_t i = 0; i < fused.size(); ++i) {
         const PGate& g = fused[i];
         sig[i] = uint32_t(g.kind & 31) | (uint32_t(g.p0 & 63) << 5) |
-                 (uint32_t(is_1q(g.kind) ? 0 : (g.p1 & 63)) << 11) | (uint32_t(g.cs & 1) << 17);
+                 (uint32_t(is_1q(g.kind) ? 0 : (g.p1 & 63)) << 11) | (uint32_t(g.cs & 1) << 17) |
+                 (uint32_t(g.cm != 0) << 18);
     }
     const bool same = m.n == n && m.cfg.tile_bits == cfg.tile_bits && m.cfg.low_bits == cfg.low_bits &&
                       m.cfg.reg_bits == cfg.reg_bits && m.cfg.coal_bits == cfg.coal_bits &&

@@ -95,6 +95,7 @@ bool is_zero(double x) { return x == 0.0; }
 // gate bit is not a register bit of the stage (a planner bug).
 template <typename R>
 bool to_device_gate(const PGate& g, const int* loc, const Stage& st, TGate<R>& t) {
+    if (g.cm) return false;   // extra controls never reach a tile pass
     int reg[32];
     for (int b = 0; b < 32; ++b) reg[b] = -1;
     for (int j = 0; j < st.nr; ++j) reg[st.rbits[j]] = j;

@@ -27,10 +27,12 @@ STATUS = {0: "QSV_OK", 1: "QSV_ERR_ARG", 2: "QSV_ERR_QUBIT", 3: "QSV_ERR_NOMEM",
           4: "QSV_ERR_HIP", 5: "QSV_ERR_DTYPE", 6: "QSV_ERR_ALIGN", 7: "QSV_ERR_SIZE",
           8: "QSV_ERR_INTERNAL"}
 
-# C layout of qsv_gate: 6 x int32, then double[32] (offset 24), 280 bytes.
+# C layout of qsv_gate: 6 x int32, double[32] (offset 24), then the extra
+# control masks cmask, cvals (uint64 at 280, 288): 296 bytes.
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("ctrl_state", "<i4"),
-                       ("axis", "<i4"), ("param", "<i4"), ("m", "<f8", (32,))], align=True)
-assert GATE_DTYPE.itemsize == 280
+                       ("axis", "<i4"), ("param", "<i4"), ("m", "<f8", (32,)),
+                       ("cmask", "<u8"), ("cvals", "<u8")], align=True)
+assert GATE_DTYPE.itemsize == 296
 
 
 class KStat(ctypes.Structure):
@@ -45,7 +47,7 @@ EXPORTS = [
     "qsv_init_basis", "qsv_apply1q", "qsv_applyC1q", "qsv_apply2q", "qsv_apply_circuit",
     "qsv_norm2", "qsv_expect_z", "qsv_inner", "qsv_prob1", "qsv_measure1", "qsv_copy_to_host",
     "qsv_copy_from_host", "qsv_adjoint", "qsv_batch_run", "qsv_profile_begin", "qsv_profile_end",
-    "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused",
+    "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused", "qsv_applyMC1q", "qsv_applyKq",
 ]
 
 
@@ -83,6 +85,8 @@ def lib():
         "qsv_apply1q": [vp, i32, vp],
         "qsv_applyC1q": [vp, i32, i32, i32, vp],
         "qsv_apply2q": [vp, i32, i32, vp],
+        "qsv_applyMC1q": [vp, i32, vp, vp, i32, vp],
+        "qsv_applyKq": [vp, i32, vp, vp],
         "qsv_apply_circuit": [vp, vp, i64, vp, i64, i32],
         "qsv_norm2": [vp, P(d)],
         "qsv_expect_z": [vp, i32, vp, vp, vp, vp],
@@ -139,6 +143,10 @@ def marshal_gates(gates: Iterable) -> np.ndarray:
             g["ctrl_state"][i] = getattr(gate, "ctrl_state", 1)
             m = _mat(gate.matrix, 4 if kind == G2Q else 2)
             g["m"][i][: m.size] = m
+        for q, v in zip(getattr(gate, "controls", ()), getattr(gate, "control_states", ())):
+            g["cmask"][i] |= np.uint64(1 << int(q))
+            if v:
+                g["cvals"][i] |= np.uint64(1 << int(q))
     return g
 
 
@@ -286,6 +294,15 @@ class State:
 
     def apply2q(self, qa: int, qb: int, u):
         self.ctx.check(lib().qsv_apply2q(self.handle, qa, qb, _ptr(_mat(u, 4))))
+
+    def applyMC1q(self, controls: Sequence[int], qt: int, u, ctrl_states: Optional[Sequence[int]] = None):
+        c = np.ascontiguousarray(list(controls), dtype=np.int32)
+        v = None if ctrl_states is None else np.ascontiguousarray(list(ctrl_states), dtype=np.int32)
+        self.ctx.check(lib().qsv_applyMC1q(self.handle, c.size, _ptr(c), _ptr(v), qt, _ptr(_mat(u, 2))))
+
+    def applyKq(self, qubits: Sequence[int], u):
+        qs = np.ascontiguousarray(list(qubits), dtype=np.int32)
+        self.ctx.check(lib().qsv_applyKq(self.handle, qs.size, _ptr(qs), _ptr(_mat(u, 2 ** qs.size))))
 
     def apply_circuit(self, gates, params=None, flags: int = 0, marshalled: Optional[np.ndarray] = None):
         g = marshalled if marshalled is not None else marshal_gates(gates)

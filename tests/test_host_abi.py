@@ -41,13 +41,16 @@ def test_status_strings():
 def test_gate_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "qsv.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(qsv_gate),'
-                   ' offsetof(qsv_gate, param), offsetof(qsv_gate, m), sizeof(qsv_kstat));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(qsv_gate),'
+                   ' offsetof(qsv_gate, param), offsetof(qsv_gate, m), sizeof(qsv_kstat),'
+                   ' offsetof(qsv_gate, cmask), offsetof(qsv_gate, cvals));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
-    size, off_param, off_m, kst = map(int, subprocess.check_output([str(exe)]).split())
-    assert size == q.qsv.GATE_DTYPE.itemsize == 280
+    size, off_param, off_m, kst, off_cm, off_cv = map(int, subprocess.check_output([str(exe)]).split())
+    assert size == q.qsv.GATE_DTYPE.itemsize == 296
+    assert off_cm == q.qsv.GATE_DTYPE.fields["cmask"][1]
+    assert off_cv == q.qsv.GATE_DTYPE.fields["cvals"][1]
     assert off_param == q.qsv.GATE_DTYPE.fields["param"][1]
     assert off_m == q.qsv.GATE_DTYPE.fields["m"][1]
     assert kst == ctypes.sizeof(q.qsv.KStat)
@@ -157,11 +160,16 @@ def _records_to_circuit(n, recs):
     for r in recs:
         m = r["m"][0::2] + 1j * r["m"][1::2]
         if r["kind"] == q.qsv.G1Q:
-            gates.append(W.g1(int(r["q0"]), m[:4].reshape(2, 2)))
+            g = W.g1(int(r["q0"]), m[:4].reshape(2, 2))
         elif r["kind"] == q.qsv.GC1Q:
-            gates.append(W.gc(int(r["q0"]), int(r["q1"]), m[:4].reshape(2, 2), int(r["ctrl_state"])))
+            g = W.gc(int(r["q0"]), int(r["q1"]), m[:4].reshape(2, 2), int(r["ctrl_state"]))
         else:
-            gates.append(W.g2(int(r["q0"]), int(r["q1"]), m.reshape(4, 4)))
+            g = W.g2(int(r["q0"]), int(r["q1"]), m.reshape(4, 4))
+        cm, cv = int(r["cmask"]), int(r["cvals"])
+        if cm:
+            cs = [qq for qq in range(n) if (cm >> qq) & 1]
+            g = W.with_controls(g, cs, [(cv >> qq) & 1 for qq in cs])
+        gates.append(g)
     return W.Circuit(n, gates)
 
 
@@ -172,6 +180,7 @@ def _records_to_circuit(n, recs):
     lambda: W.hea_cz_ring(13, 3, seed=8),
     lambda: W.qft(12),
     lambda: W.config1(),
+    lambda: W.random_multicontrol(13, 150, seed=9),
 ])
 @pytest.mark.parametrize("dtype,tb,lb", [(q.QSV_C128, 0, 0), (q.QSV_C128, 10, 2), (q.QSV_C64, 12, 4),
                                          (q.QSV_C64, 13, 0)])

@@ -155,6 +155,40 @@ def random_mix(n: int, ngates: int, seed: int, name: str = "random_mix") -> Circ
     return Circuit(n, gates, np.zeros(0), obs, name)
 
 
+def random_multicontrol(n: int, ngates: int, seed: int, max_controls: int = 3,
+                        name: str = "random_multicontrol") -> Circuit:
+    """The 50/25/25 mix of `random_mix`, each gate given 0..max_controls extra
+    controls (uniform count, on uniform distinct further qubits, each with a
+    uniform control state), plus Toffolis (X with two controls in state 1)
+    on every fifth gate.  Observable sum_i Z_i."""
+    if n < 3:
+        raise ValueError("random_multicontrol needs n >= 3")
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = []
+    for k in range(ngates):
+        if k % 5 == 4:
+            c0, c1, t = rng.choice(n, size=3, replace=False)
+            gates.append(toffoli(c0, c1, t))
+            continue
+        r = rng.random()
+        if r < 0.5:
+            g = g1(rng.integers(n), haar_unitary(2, rng))
+        elif r < 0.75:
+            qc, qt = rng.choice(n, size=2, replace=False)
+            g = gc(qc, qt, haar_unitary(2, rng), int(rng.integers(2)))
+        else:
+            qa, qb = rng.choice(n, size=2, replace=False)
+            g = g2(qa, qb, haar_unitary(4, rng))
+        free = [q for q in range(n) if q not in g.qubits]
+        nc = int(rng.integers(0, min(max_controls, len(free)) + 1))
+        if nc:
+            cs = rng.choice(free, size=nc, replace=False)
+            g = with_controls(g, cs, rng.integers(0, 2, size=nc))
+        gates.append(g)
+    obs = [((q,), 1.0) for q in range(n)]
+    return Circuit(n, gates, np.zeros(0), obs, f"{name}_n{n}_g{ngates}")
+
+
 def config1(seed: int = 1001) -> Circuit:
     """10 qubits, 200 gates of the 50/25/25 mix; observables <Z_i> for all i."""
     return random_mix(10, 200, seed, "config1_mix_n10_g200")

@@ -292,6 +292,9 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128",
+                    help="precision of the primary workload (profiling aid; the reported "
+                         "metric is defined on complex128)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of 2^k complex128 amplitudes (counter calibration)")
     args = ap.parse_args()
@@ -318,11 +321,13 @@ def main():
         return
 
     log(f"primary: n={args.n} c128 steps={args.steps} warmup={args.warmup}")
-    r = primary(q, W, args.n, q.QSV_C128, args.steps, args.warmup)
+    c64 = args.dtype == "c64"
+    r = primary(q, W, args.n, q.QSV_C64 if c64 else q.QSV_C128, args.steps, args.warmup)
     value = r["gates"] * args.steps / r["seconds"]
-    roof = kernel_roofline(r["prof"], "tile_pass_c128", args.steps, r["flops_per_step"], "f64")
+    roof = kernel_roofline(r["prof"], "tile_pass_c64" if c64 else "tile_pass_c128", args.steps,
+                           r["flops_per_step"], "f32" if c64 else "f64")
     if roof is not None:
-        roof["traffic"] = measured_traffic(args.n)
+        roof["traffic"] = None if c64 else measured_traffic(args.n)
     log(f"primary: {value:.1f} gates/s, roofline {roof}")
     extras = {"norm_after": r["norm"], "zz_0_last": r["zz"],
               "kernels_c128": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
@@ -359,11 +364,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if c64 else "f64",
         "data": "synthetic",
         "config": {"workload": f"layered CNOT-brick circuit, {args.n} qubits, 20 layers "
                                f"({r['gates']} gates: Haar 1q on every qubit + CNOT even/odd "
-                               f"pairs), complex128, seed 3002; step = init + circuit + norm "
+                               f"pairs), {'complex64' if c64 else 'complex128'}, seed 3002; step = init + circuit + norm "
                                f"+ <Z0 Z{args.n - 1}>",
                    "n_qubits": args.n, "gates": r["gates"], "state_bytes": 16 * 2 ** args.n},
         "roofline": roof,

@@ -3,6 +3,9 @@
     python -m paper_2303_00123_amd.profsum stats <kernel_stats.csv> [--cmd "..."]
         Markdown table of per-kernel call counts and durations.
 
+    python -m paper_2303_00123_amd.profsum counters --kernel k_tile <csv> [<csv> ...]
+        Average per dispatch of every counter of a kernel over --pmc runs.
+
     python -m paper_2303_00123_amd.profsum traffic --kernel k_tile \\
         --fetch <dir>/..._counter_collection.csv --write <...csv> \\
         --copy-fetch <...csv> --copy-write <...csv> --copy-bytes B \\
@@ -74,12 +77,36 @@ def counter_per_dispatch(path: str, kernel_substr: str, counter: str):
     return sum(vals) / len(vals), len(vals)
 
 
+def counters_markdown(paths, kernel_substr: str, cmd: str = "") -> str:
+    """Average per dispatch of every counter found for a kernel in one or
+    more rocprofv3 counter_collection CSVs (one --pmc pass each)."""
+    acc = {}
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if kernel_substr in r["Kernel_Name"]:
+                    acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = []
+    if cmd:
+        out.append(f"Command: `{cmd}`\n")
+    out.append("| counter | dispatches | average per dispatch |")
+    out.append("|---|---|---|")
+    for k in sorted(acc):
+        v = acc[k]
+        out.append(f"| {k} | {len(v)} | {sum(v) / len(v):.6g} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--cmd", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--cmd", default="")
+    c.add_argument("csv", nargs="+")
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
     t.add_argument("--fetch", required=True)
@@ -94,6 +121,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd_ == "stats":
         sys.stdout.write(stats_markdown(a.csv, a.cmd))
+        return
+    if a.cmd_ == "counters":
+        sys.stdout.write(counters_markdown(a.csv, a.kernel, a.cmd))
         return
     kf, nf = counter_per_dispatch(a.fetch, a.kernel, "FETCH_SIZE")
     kw, nw = counter_per_dispatch(a.write, a.kernel, "WRITE_SIZE")

@@ -187,3 +187,34 @@ def test_argument_errors_leave_state(q, ctx):
     st.free()
     with pytest.raises(q.QsvError):
         ctx.batch_run([W.Circuit(4, [W.toffoli(0, 1, 2)], np.zeros(0), [((0,), 1.0)])], q.QSV_C128)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_qasm_program_through_the_library(q, ctx, dtype):
+    """An OpenQASM 2.0 program (QFT on 12 qubits, then Toffoli, controlled
+    swap and a user-defined gate) lowered by the front-end and run by
+    qsv_apply_circuit, against the oracle on the same records and, for the
+    QFT part, against numpy's FFT."""
+    from paper_2303_00123_amd import qasm
+    dt = q.QSV_C128 if dtype == "c128" else q.QSV_C64
+    n = 12
+    lines = ["OPENQASM 2.0;", 'include "qelib1.inc";', f"qreg q[{n}];"]
+    for i in range(n):
+        lines.append(f"h q[{i}];")
+        for j in range(2, n - i + 1):
+            lines.append(f"cu1(-2*pi/2^{j}) q[{j + i - 1}], q[{i}];")
+    for i in range(n // 2):
+        lines.append(f"swap q[{i}], q[{n - 1 - i}];")
+    qft = qasm.parse("\n".join(lines))
+    phi = W.random_state(n, 580)
+    got = run_gpu(q, ctx, n, dt, phi, lambda st: st.apply_circuit(None, marshalled=qft.gates))
+    check(q, got, np.fft.fft(phi) / np.sqrt(2 ** n), dt)
+    tail = qasm.parse("\n".join(lines[:3] + [
+        "gate g(a) x, y { ry(a) x; cz x, y; }", "ccx q[0], q[11], q[5];", "cswap q[3], q[1], q[10];",
+        "g(0.3) q[2], q[7];", "c3x q[4], q[6], q[8], q[9];"]))
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import test_host_abi as H
+    ref = O.run(H._records_to_circuit(n, tail.gates), phi)
+    got = run_gpu(q, ctx, n, dt, phi, lambda st: st.apply_circuit(None, marshalled=tail.gates))
+    check(q, got, ref, dt)

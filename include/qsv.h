@@ -218,6 +218,22 @@ qsv_status qsv_norm2(qsv_state st, double* out);
 qsv_status qsv_expect_z(qsv_state st, int nterms, const uint64_t* qmasks, const double* w,
                         double* out_terms, double* out_sum);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * per-term values of qsv_expect_z, out_dev[k] = <psi| Z^{qmasks[k]} |psi>
+ * for k < nterms, written to out_dev, a caller-owned device array of at
+ * least nterms doubles (8-byte aligned).  Same kernels and summation order
+ * as qsv_expect_z, so the values are bit-identical to its out_terms.  The
+ * call allocates nothing and does not synchronise: it enqueues kernels on
+ * the context's stream and returns (no memset, no copy, so it may be
+ * captured into a hipGraph).  qmasks is read on the host before the call
+ * returns.  Scratch: a fixed array of 256 KiB + 128 B per GPU, held until
+ * the process ends and shared by every call on that GPU (from any context);
+ * each call overwrites all of it that it reads, so nothing needs clearing,
+ * but calls that overlap in time on one GPU (different streams or threads)
+ * race on it and must be ordered by the caller.  1 <= nterms <= 4096. */
+qsv_status qsv_expect_z_dev(qsv_state st, int nterms, const uint64_t* qmasks, double* out_dev);
+
 /* <a|b> = sum_x conj(a_x) b_x (out[0] = re, out[1] = im).  a and b must have
  * the same n; their dtypes may differ (the c64 operand is widened). */
 qsv_status qsv_inner(qsv_state a, qsv_state b, double* out);

@@ -269,6 +269,9 @@ qsv_status qsv_ctx_create(void* hip_stream, qsv_ctx* out) {
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_red), 4096, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->plan_copied, hipEventDisableTiming);
+        // the allocation-free reduction's scratch on this device (its
+        // address, looked up once per device)
+        if (e == hipSuccess) e = reduce_scratch_init(ctx->device);
         if (e == hipSuccess) e = hipEventRecord(ctx->plan_copied, ctx->stream);
         if (e != hipSuccess) {
             qsv_status st = e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP;
@@ -699,6 +702,28 @@ qsv_status qsv_expect_z(qsv_state st, int nterms, const uint64_t* qmasks, const 
         for (int t = 0; t < nterms; ++t) sum += (w ? w[t] : 1.0) * terms[t];
         if (out_terms) std::memcpy(out_terms, terms.data(), sizeof(double) * nterms);
         if (out_sum) *out_sum = sum;
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
+}
+
+qsv_status qsv_expect_z_dev(qsv_state st, int nterms, const uint64_t* qmasks, double* out_dev) {
+    try {
+        if (qsv_status s = check_state(st)) return s;
+        qsv_ctx ctx = st->ctx;
+        if (nterms < 1 || nterms > 4096 || !qmasks)
+            return fail(ctx, QSV_ERR_ARG, "need 1 <= nterms <= 4096 and a mask array");
+        if (!out_dev) return fail(ctx, QSV_ERR_ARG, "null output array");
+        if (reinterpret_cast<uintptr_t>(out_dev) % sizeof(double))
+            return fail(ctx, QSV_ERR_ALIGN, "output array not 8-byte aligned");
+        const int n = st->n;
+        for (int t = 0; t < nterms; ++t)
+            if (n < 64 && (qmasks[t] >> n)) return fail(ctx, QSV_ERR_QUBIT, "a term names a qubit >= n");
+        HIP_OR_FAIL(ctx, reduce_zstrings_dev(ctx, st->ptr, n, st->dtype, nterms, qmasks, out_dev),
+                    "expect_z_dev");
         return QSV_OK;
     } catch (const std::bad_alloc&) {
         return QSV_ERR_NOMEM;

@@ -307,6 +307,13 @@ hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<
 // Z-string sums: out[t] = sum_x |s_x|^2 (-1)^{popcount(x & pmask[t])}, t < nt.
 hipError_t reduce_zstrings(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
                            const uint64_t* pmasks, double* out);
+// The same sums for qubit masks qmasks[0..nt) (bit q = qubit q), written to
+// out_dev (device memory) with no allocation and no host synchronisation;
+// partials live in a fixed per-GPU array whose address reduce_scratch_init
+// (called once per device, with that device current) looks up.
+hipError_t reduce_scratch_init(int device);
+hipError_t reduce_zstrings_dev(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
+                               const uint64_t* qmasks, double* out_dev);
 // out[0] = sum over x with bit p clear, out[1] = with bit p set, of |s_x|^2.
 hipError_t reduce_bit_split(qsv_ctx ctx, const void* s, int n, int dtype, int p, double* out);
 // <a|b>

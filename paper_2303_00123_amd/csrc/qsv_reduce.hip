@@ -2,6 +2,8 @@
 // probabilities, inner products, and measurement collapse.  Accumulation is
 // FP64 for both state precisions, in a fixed two-stage tree (per-block
 // partials, then one block), so results are bit-reproducible for a given n.
+#include <mutex>
+
 #include "qsv_common.h"
 #include "qsv_internal.h"
 
@@ -266,7 +268,81 @@ hipError_t collapse_t(qsv_ctx ctx, void* s, int n, int p, int keep, double scale
     return hipGetLastError();
 }
 
+// Copy the first nt stage-2 results to the caller's array.
+__global__ void k_copy_terms(const double* __restrict__ res, int nt, double* __restrict__ out) {
+    if (int(threadIdx.x) < nt) out[threadIdx.x] = res[threadIdx.x];
+}
+
 }  // namespace
+
+// ------------------------------------------- allocation-free Z strings
+// The allocation-free entry point keeps its stage-1 partials (at most 2048
+// blocks x 16 terms) and the 16 stage-2 results of a pass in this fixed
+// array instead of context memory: 256 KiB + 128 B of FP64.  Each GPU holds
+// its own copy until the process ends.  Host code never uses the array's
+// name as an address (it is a host-side stand-in): each device's address is
+// looked up once with hipGetSymbolAddress and kept in g_scratch_dev.
+constexpr size_t kScratchDoubles = size_t(kMaxBlocks) * kTermsPerPass + kTermsPerPass;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+void* scratch_dev(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+template <typename R>
+hipError_t zstrings_dev_t(qsv_ctx ctx, const void* s, int n, int nt, const uint64_t* qmasks,
+                          double* out_dev, double* sp) {
+    using V = typename V2T<R>::type;
+    const uint64_t N = uint64_t(1) << n;
+    const unsigned G = red_blocks(N);
+    if (size_t(G) * kTermsPerPass + kTermsPerPass > kScratchDoubles) return hipErrorInvalidValue;
+    const uint64_t chunk = (N + G - 1) / G;
+    double* partials = sp;
+    double* res = sp + size_t(kMaxBlocks) * kTermsPerPass;
+    for (int t0 = 0; t0 < nt; t0 += kTermsPerPass) {
+        ZMasks zm{};
+        zm.nt = nt - t0 < kTermsPerPass ? nt - t0 : kTermsPerPass;
+        // qubit q -> index bit n-1-q (Definition 1)
+        for (int t = 0; t < zm.nt; ++t)
+            for (int q = 0; q < n; ++q)
+                if ((qmasks[t0 + t] >> q) & 1) zm.m[t] |= uint64_t(1) << (n - 1 - q);
+        hipLaunchKernelGGL(k_zstr<R>, dim3(G), dim3(kThreads), 0, ctx->stream,
+                           static_cast<const V*>(s), N, chunk, zm, partials);
+        hipLaunchKernelGGL(k_final<kTermsPerPass>, dim3(1), dim3(kThreads), 0, ctx->stream,
+                           partials, int(G), kTermsPerPass, res);
+        hipLaunchKernelGGL(k_copy_terms, dim3(1), dim3(64), 0, ctx->stream, res, zm.nt, out_dev + t0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t reduce_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+    return hipSuccess;
+}
+
+hipError_t reduce_zstrings_dev(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
+                               const uint64_t* qmasks, double* out_dev) {
+    double* sp = static_cast<double*>(scratch_dev(ctx->device));
+    if (!sp) return hipErrorNotInitialized;
+    return dtype == QSV_C128 ? zstrings_dev_t<double>(ctx, s, n, nt, qmasks, out_dev, sp)
+                             : zstrings_dev_t<float>(ctx, s, n, nt, qmasks, out_dev, sp);
+}
 
 hipError_t reduce_zstrings(qsv_ctx ctx, const void* s, int n, int dtype, int nt,
                            const uint64_t* pmasks, double* out) {

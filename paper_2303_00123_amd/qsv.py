@@ -48,6 +48,7 @@ EXPORTS = [
     "qsv_norm2", "qsv_expect_z", "qsv_inner", "qsv_prob1", "qsv_measure1", "qsv_copy_to_host",
     "qsv_copy_from_host", "qsv_adjoint", "qsv_batch_run", "qsv_profile_begin", "qsv_profile_end",
     "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused", "qsv_applyMC1q", "qsv_applyKq",
+    "qsv_expect_z_dev",
 ]
 
 
@@ -90,6 +91,7 @@ def lib():
         "qsv_apply_circuit": [vp, vp, i64, vp, i64, i32],
         "qsv_norm2": [vp, P(d)],
         "qsv_expect_z": [vp, i32, vp, vp, vp, vp],
+        "qsv_expect_z_dev": [vp, i32, vp, vp],
         "qsv_inner": [vp, vp, vp],
         "qsv_prob1": [vp, i32, P(d)],
         "qsv_measure1": [vp, i32, d, P(i32)],

@@ -40,24 +40,31 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20, seed: int = 3002):
+def run_circuit(q, c, dtype: int, steps: int, warmup: int, jit: bool = False, obs=None):
+    """Time `steps` runs of circuit c from |0...0> (after `warmup` untimed
+    runs, which also plan and, with jit, compile the pass kernels); each step
+    ends with the norm and the observable's Z strings in one reduction."""
     import torch
-    c = W.layered_cnot_brick(n, layers, seed)
+    n = c.n
     g = q.marshal_gates(c.gates)
     ctx = q.Context()
+    if jit:
+        ctx.set_jit(1)
     st = q.State(ctx, n, dtype)
     # the norm is the Z string over no qubits: one reduction pass gives
-    # both it and <Z0 Z_{n-1}>
-    obs = [((), 1.0)] + list(c.observable)
+    # both it and the observable's terms
+    obs = [((), 1.0)] + list(c.observable if obs is None else obs)
 
     def step():
         # |0...0>, then the circuit: the first tile pass makes |0...0> itself
-        st.apply_circuit(None, marshalled=g, flags=q.FLAG_FROM_ZERO)
+        st.apply_circuit(None, c.params, marshalled=g, flags=q.FLAG_FROM_ZERO)
         return st.expect_z(obs)
 
+    t0 = time.perf_counter()
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
     ctx.profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -66,13 +73,43 @@ def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20,
     t1 = time.perf_counter()
     prof = ctx.profile_end()
     norm = st.norm2()
+    jk, js = ctx.jit_stats()
     st.free()
     del st
     ctx.close()
     torch.cuda.empty_cache()
     flops = sum(gate_flops_per_amp(x) for x in c.gates) * float(2 ** n)
+    _, pas = q.plan_fused(n, c.gates, c.params, dtype)
     return {"gates": len(c.gates), "seconds": t1 - t0, "prof": prof, "norm": norm,
-            "norm_in_step": float(terms[0]), "zz": float(terms[1]), "flops_per_step": flops}
+            "norm_in_step": float(terms[0]), "terms": [float(x) for x in terms[1:]],
+            "flops_per_step": flops, "warmup_s": t_warm, "jit_kernels": jk, "jit_compile_s": js,
+            "passes": int(pas.max()) + 1 if len(pas) else 0}
+
+
+def primary(q, W, n: int, dtype: int, steps: int, warmup: int, layers: int = 20, seed: int = 3002,
+            jit: bool = False):
+    c = W.layered_cnot_brick(n, layers, seed)
+    r = run_circuit(q, c, dtype, steps, warmup, jit)
+    r["zz"] = r["terms"][0]
+    return r
+
+
+def circuit_extra(q, c, dtype: int, steps: int, warmup: int, jit: bool, label: str):
+    """gates/s and the tile-pass roofline of one circuit (an `extras` entry)."""
+    c64 = dtype == q.QSV_C64
+    r = run_circuit(q, c, dtype, steps, warmup, jit)
+    out = {"workload": label, "gates": r["gates"], "passes": r["passes"],
+           "gates_per_s": round(r["gates"] * steps / r["seconds"], 2),
+           "ms_per_circuit": round(r["seconds"] / steps * 1e3, 3),
+           "norm": r["norm"], "jit": jit}
+    if jit:
+        out["jit_kernels"] = r["jit_kernels"]
+        out["jit_compile_s"] = round(r["jit_compile_s"], 2)
+    roof = kernel_roofline(r["prof"], "tile_pass_c64" if c64 else "tile_pass_c128", steps,
+                           r["flops_per_step"], "f32" if c64 else "f64")
+    if roof is not None:
+        out["roofline"] = roof
+    return out
 
 
 def gate_flops_per_amp(gate) -> float:
@@ -127,10 +164,10 @@ def kernel_roofline(prof: dict, name: str, steps: int, flops_per_step: float, dt
     return out
 
 
-def measured_traffic(n: int):
+def measured_traffic(n: int, jit: bool = False):
     """HBM bytes per tile-pass launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, if it was measured on the current kernel sources and workload."""
-    path = os.path.join(ROOT, "profiles", f"traffic_tile_pass_c128_n{n}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_tile_pass_c128_n{n}{'_jit' if jit else ''}.json")
     if not os.path.exists(path):
         return None
     from paper_2303_00123_amd import profsum
@@ -141,7 +178,38 @@ def measured_traffic(n: int):
     return rec.get("traffic_bytes_per_launch")
 
 
-def unfused_sweep(q, W, n: int, every: int = 1):
+def jit_usable(q) -> bool:
+    """True if this host has the device compiler the specialised pass kernels need."""
+    ctx = q.Context()
+    try:
+        ctx.set_jit(1)
+        return True
+    except q.QsvError:
+        return False
+    finally:
+        ctx.close()
+
+
+def size_sweep(q, W, sizes=(16, 20, 24, 28, 30, 32)):
+    """Time per circuit against the qubit count for the paper's two benchmark
+    circuits (QFT and a Trotter TFXY chain, 5 steps), both precisions; the
+    interpreting tile kernel (no compile step per size)."""
+    out = {}
+    for name, make in (("qft", lambda n: W.qft(n)), ("trotter_tfxy_5", lambda n: W.trotter_tfxy(n, 5, 4000 + n))):
+        rows = []
+        for n in sizes:
+            c = make(n)
+            for dt, tag in ((q.QSV_C128, "c128"), (q.QSV_C64, "c64")):
+                r = run_circuit(q, c, dt, 2, 1, False, obs=[])
+                rows.append({"n": n, "dtype": tag, "gates": r["gates"], "passes": r["passes"],
+                             "ms": round(r["seconds"] / 2 * 1e3, 3),
+                             "gates_per_s": round(r["gates"] * 2 / r["seconds"], 1)})
+            log(f"sweep {name} n={n}")
+        out[name] = rows
+    return out
+
+
+def unfused_sweep(q, W, n: int, every: int = 1, dtype=None):
     """Average bandwidth of the one-pass-per-gate kernels (Algs. 1-3).
 
     A controlled gate moves half the state (2^n * 16 bytes, its algorithmic
@@ -162,7 +230,7 @@ def unfused_sweep(q, W, n: int, every: int = 1):
         gates.append(W.g2(qb, n - 1 - qb if n - 1 - qb != qb else qb + 1, W.haar_unitary(4, rng)))
     low = [W.gc(n - 1, 0, W.haar_unitary(2, rng)) for _ in range(4 if every == 1 else 2)]   # control at index bit 0
     ctx = q.Context()
-    st = q.State(ctx, n, q.QSV_C128)
+    st = q.State(ctx, n, q.QSV_C128 if dtype is None else dtype)
     st.init_basis(0)
     out = {}
     for gl, tag in ((gates, ""), (low, "_ctrl_bit0")):
@@ -255,9 +323,31 @@ def batch_bench(q, W, dtype, reps: int = 5):
             "circuits_per_s_gpu": round(len(circs) / (gpu_ms / 1e3), 1)}
 
 
-def cpu_baseline(W, n: int, budget_s: float = 15.0):
+def host_cpu():
+    """CPU model, physical cores and hardware threads of this host (lscpu)."""
+    import subprocess
+    info = {"model": None, "physical_cores": None, "threads": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        cps, sockets = kv.get("Core(s) per socket"), kv.get("Socket(s)")
+        if cps and sockets:
+            info["physical_cores"] = int(cps) * int(sockets)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(W, n: int, budget_s: float = 15.0, threads: int = 0):
     import numpy as np
     import oracle as O
+    if threads:
+        O.set_num_threads(threads)
     c = W.layered_cnot_brick(n, 20, 3002)
     s = np.zeros(2 ** n, dtype=np.complex128)
     s[0] = 1.0
@@ -278,10 +368,12 @@ def cpu_baseline(W, n: int, budget_s: float = 15.0):
         done += 1
         k += 1
         log(f"cpu oracle gate {k}/{len(gates)}: {t_total:.1f} s")
-    return {"value": round(done / t_total, 4), "unit": "gates/s", "cores": O.num_threads(),
+    used = O.num_threads()
+    return {"value": round(done / t_total, 4), "unit": "gates/s", "cores": used,
             "kind": "oracle",
             "sample": f"gates 2..{k} of the same {n}-qubit 1180-gate circuit, FP64 oracle "
-                      f"(out-of-place Kronecker-definition loops, OpenMP), {t_total:.1f} s"}
+                      f"(out-of-place Kronecker-definition loops, OpenMP, {used} threads), "
+                      f"{t_total:.1f} s"}
 
 
 def main():
@@ -292,6 +384,9 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-jit", action="store_true",
+                    help="run the fused passes with the interpreting tile kernel only")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128",
                     help="precision of the primary workload (profiling aid; the reported "
                          "metric is defined on complex128)")
@@ -320,39 +415,65 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel() * 16, "copies": 3}))
         return
 
-    log(f"primary: n={args.n} c128 steps={args.steps} warmup={args.warmup}")
+    jit = not args.no_jit and jit_usable(q)
+    log(f"primary: n={args.n} {args.dtype} steps={args.steps} warmup={args.warmup} jit={jit}")
     c64 = args.dtype == "c64"
-    r = primary(q, W, args.n, q.QSV_C64 if c64 else q.QSV_C128, args.steps, args.warmup)
+    r = primary(q, W, args.n, q.QSV_C64 if c64 else q.QSV_C128, args.steps, args.warmup, jit=jit)
     value = r["gates"] * args.steps / r["seconds"]
     roof = kernel_roofline(r["prof"], "tile_pass_c64" if c64 else "tile_pass_c128", args.steps,
                            r["flops_per_step"], "f32" if c64 else "f64")
     if roof is not None:
-        roof["traffic"] = None if c64 else measured_traffic(args.n)
+        roof["traffic"] = None if c64 else measured_traffic(args.n, jit)
     log(f"primary: {value:.1f} gates/s, roofline {roof}")
-    extras = {"norm_after": r["norm"], "zz_0_last": r["zz"],
+    extras = {"norm_after": r["norm"], "zz_0_last": r["zz"], "passes": r["passes"],
+              "pass_kernels": "specialised per pass structure" if jit else "interpreting",
               "kernels_c128": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
                                for k, v in r["prof"].items()}}
+    if jit:
+        extras["jit"] = {"kernels": r["jit_kernels"], "compile_s": round(r["jit_compile_s"], 2),
+                         "warmup_s": round(r["warmup_s"], 2)}
     if not args.no_extras:
         log("extras: complex64")
         s64 = max(2, args.steps // 2)
-        r64 = primary(q, W, args.n, q.QSV_C64, s64, 1)
+        r64 = primary(q, W, args.n, q.QSV_C64, s64, 1, jit=jit)
         extras["c64"] = {"gates_per_s": round(r64["gates"] * s64 / r64["seconds"], 2),
+                         "passes": r64["passes"],
                          "roofline": kernel_roofline(r64["prof"], "tile_pass_c64", s64,
                                                      r64["flops_per_step"], "f32")}
+        log("extras: 1000-gate random mix at 30 qubits")
+        mix = W.random_mix(30, 1000, 3001, "random_mix")
+        extras["random_mix_n30"] = {
+            "c128": circuit_extra(q, mix, q.QSV_C128, 3, 1, jit, "50/25/25 Haar 1q / controlled Haar / "
+                                  "Haar 2q, 1000 gates, 30 qubits, complex128, seed 3001"),
+            "c64": circuit_extra(q, mix, q.QSV_C64, 3, 1, jit, "the same circuit, complex64")}
+        log("extras: random Haar pairs at 32 qubits")
+        hp = W.layered_haar_pairs(32, 10, 1003)
+        extras["haar_pairs_n32"] = {
+            "c128": circuit_extra(q, hp, q.QSV_C128, 2, 1, jit, "10 layers of Haar 1q on every qubit + "
+                                  "Haar 2q on a random matching, 32 qubits (64 GiB), complex128, seed 1003"),
+            "c64": circuit_extra(q, hp, q.QSV_C64, 2, 1, jit, "the same circuit, complex64 (32 GiB)")}
         log("extras: unfused sweep")
         extras["unfused_c128"] = unfused_sweep(q, W, args.n)
+        extras["unfused_c64"] = unfused_sweep(q, W, args.n, dtype=q.QSV_C64)
         if args.n == 30:
             log("extras: unfused sweep at 32 qubits")
             extras["unfused_c128_n32"] = unfused_sweep(q, W, 32, every=4)
         log("extras: adjoint ratio")
         extras["adjoint"] = adjoint_ratio(q, W)
+        extras["adjoint_c64"] = adjoint_ratio(q, W, dtype=q.QSV_C64)
         log("extras: batch")
         extras["batch_c128"] = batch_bench(q, W, q.QSV_C128)
         extras["batch_c64"] = batch_bench(q, W, q.QSV_C64)
+        if not args.no_sweep:
+            log("extras: QFT and Trotter time vs qubits")
+            extras["sweep"] = size_sweep(q, W)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
         cpu = cpu_baseline(W, args.n)
+        extras["host_cpu"] = host_cpu()
+        log("cpu baseline, one thread")
+        extras["cpu_1thread"] = cpu_baseline(W, args.n, budget_s=10.0, threads=1)
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -327,6 +327,31 @@ qsv_status qsv_profile_end(qsv_ctx ctx, qsv_kstat* out, int max, int* count);
 qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int reg_bits,
                         int lds_rounds);
 
+/* Specialised tile-pass kernels.  mode 1: each fused pass of
+ * qsv_apply_circuit on this context runs a kernel generated for that pass's
+ * structure (gate kinds and register bits, stage mappings, LDS and global
+ * offsets as constants; the matrices are still read from device memory), so
+ * each gate is a direct call of its register body, updated in place, instead
+ * of an interpreted opcode.  The first run of a new structure compiles its
+ * passes with the ROCm device compiler in child processes (several at once;
+ * seconds per pass) and keeps them on the context; circuits with the same
+ * structure and other angles reuse them.  A pass whose kernel cannot be
+ * built (or would spill) runs the interpreting kernel.  mode 0 (the
+ * default; the environment variable QSV_JIT=1 sets 1 at context creation):
+ * the interpreting kernel only.  QSV_ERR_ARG if mode is 1 and no compiler is
+ * found (QSV_JIT_CLANG, else $ROCM_PATH/llvm/bin/clang++, else
+ * /opt/rocm/llvm/bin/clang++). */
+qsv_status qsv_set_jit(qsv_ctx ctx, int mode);
+/* Kernels compiled so far on ctx and the wall time spent compiling them. */
+qsv_status qsv_jit_stats(qsv_ctx ctx, int* kernels, double* compile_seconds);
+/* Host-only: the generated source of fused pass `pass` of an n-qubit
+ * circuit (n >= 10) planned with the default tile shape for dtype (no device
+ * work).  *len receives its length; buf (cap bytes, may be NULL) receives it
+ * NUL-terminated, else QSV_ERR_SIZE.  QSV_ERR_ARG if the pass is a single
+ * gate or out of range. */
+qsv_status qsv_jit_source(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
+                          int64_t nparams, int64_t pass, char* buf, size_t cap, size_t* len);
+
 /* Host-only query of the exact gate sequence the tile kernels would apply for
  * qsv_apply_circuit (no device work; needs no GPU): gates grouped into passes
  * and register stages, with the 1-qubit gates of a stage multiplied into the

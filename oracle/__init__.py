@@ -83,6 +83,7 @@ def lib():
         L.orc_finite_diff.argtypes = [i, i64, vp, vp, i, i, vp, d, i, vp, vp, vp, vp, vp]
         L.orc_product_amplitude.argtypes = [i, vp, u64, vp]
         L.orc_num_threads.restype = i
+        L.orc_set_num_threads.argtypes = [i]
         _lib = L
     return _lib
 
@@ -102,6 +103,10 @@ def _mat(u: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    lib().orc_set_num_threads(int(t))
 
 
 # ------------------------------------------------------------ single gates

@@ -441,6 +441,17 @@ void orc_product_amplitude(int n, const double* qstates, uint64_t x, double* out
     out[1] = cimag(a);
 }
 
+/* Thread count of the OpenMP loops (the benchmark's CPU baseline times the
+ * oracle on one thread and on every core). */
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

@@ -5,5 +5,6 @@ this package is its Python binding.  Nothing here computes amplitudes.
 """
 from .qsv import (  # noqa: F401
     QSV_C64, QSV_C128, FLAG_NO_FUSE, FLAG_FORWARD, FLAG_CAPTURE_GRAPH, FLAG_TUNE, FLAG_FROM_ZERO,
-    Context, State, BatchSpec, QsvError, adjoint, plan_circuit, plan_fused, lib, marshal_gates, observable_arrays, EXPORTS,
+    Context, State, BatchSpec, QsvError, adjoint, plan_circuit, plan_fused, jit_source, lib, marshal_gates,
+    observable_arrays, EXPORTS,
 )

@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation, lowering of gates to index-bit
 // positions, dispatch to the HIP launchers, error mapping.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -272,6 +273,8 @@ qsv_status qsv_ctx_create(void* hip_stream, qsv_ctx* out) {
         // the allocation-free reduction's scratch on this device (its
         // address, looked up once per device)
         if (e == hipSuccess) e = reduce_scratch_init(ctx->device);
+        if (const char* j = std::getenv("QSV_JIT"))
+            ctx->jit_mode = (std::atoi(j) != 0 && jit_available()) ? 1 : 0;
         if (e == hipSuccess) e = hipEventRecord(ctx->plan_copied, ctx->stream);
         if (e != hipSuccess) {
             qsv_status st = e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_HIP;
@@ -320,6 +323,7 @@ qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
         if (ctx->h_batch) hipHostFree(ctx->h_batch);
         if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
         if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
+        jit_release(ctx);
         delete ctx;
         return QSV_OK;
     } catch (const std::bad_alloc&) {
@@ -939,6 +943,59 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int
             return fail(ctx, s, err);
         (dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64) = cfg;
         return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
+}
+
+qsv_status qsv_set_jit(qsv_ctx ctx, int mode) {
+    try {
+        if (!ctx) return QSV_ERR_ARG;
+        if (mode != 0 && mode != 1) return fail(ctx, QSV_ERR_ARG, "mode must be 0 or 1");
+        if (mode == 1 && !jit_available())
+            return fail(ctx, QSV_ERR_ARG, "no ROCm device compiler found (QSV_JIT_CLANG, ROCM_PATH)");
+        if (mode != ctx->jit_mode) {
+            ctx->jit_mode = mode;
+            ctx->plan_resident = false;   // the next run rebuilds its kernel table
+            ctx->jit_plan_fns.clear();
+        }
+        return QSV_OK;
+    } catch (const std::bad_alloc&) {
+        return QSV_ERR_NOMEM;
+    } catch (...) {
+        return QSV_ERR_INTERNAL;
+    }
+}
+
+qsv_status qsv_jit_stats(qsv_ctx ctx, int* kernels, double* compile_seconds) {
+    if (!ctx) return QSV_ERR_ARG;
+    if (kernels) *kernels = ctx->jit_compiled;
+    if (compile_seconds) *compile_seconds = ctx->jit_compile_s;
+    return QSV_OK;
+}
+
+qsv_status qsv_jit_source(int n, int dtype, const qsv_gate* g, int64_t ng, const double* params,
+                          int64_t nparams, int64_t pass, char* buf, size_t cap, size_t* len) {
+    try {
+        if (!valid_dtype(dtype)) return QSV_ERR_DTYPE;
+        if (n < kMinTileBits || n > kMaxQubits) return QSV_ERR_SIZE;
+        if (ng < 0 || (ng > 0 && !g) || !len || pass < 0) return QSV_ERR_ARG;
+        std::vector<PGate> pg;
+        if (qsv_status s = lower(nullptr, n, g, ng, params, nparams, pg)) return s;
+        pg = prefuse(pg);
+        const TileConfig cfg = dtype == QSV_C128 ? TileConfig{13, 3, 5, 3, 1} : TileConfig{13, 4, 5, 4, 1};
+        std::vector<Pass> passes = plan_passes(n, pg, cfg);
+        if (pass >= int64_t(passes.size()) || passes[size_t(pass)].single) return QSV_ERR_ARG;
+        const Pass& ps = passes[size_t(pass)];
+        std::vector<char> rec(pass_record_bytes(dtype, ps), 0);
+        if (!write_pass_record(dtype, rec.data(), pg, ps)) return QSV_ERR_INTERNAL;
+        const std::string src = jit_pass_source(dtype, rec.data(), ps.split, "qsv_pass");
+        if (src.empty()) return QSV_ERR_INTERNAL;
+        *len = src.size();
+        if (buf && cap > src.size()) std::memcpy(buf, src.c_str(), src.size() + 1);
+        return (buf && cap <= src.size()) ? QSV_ERR_SIZE : QSV_OK;
     } catch (const std::bad_alloc&) {
         return QSV_ERR_NOMEM;
     } catch (...) {

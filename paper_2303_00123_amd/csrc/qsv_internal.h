@@ -177,6 +177,15 @@ struct PlanMemo {
 };
 }  // namespace qsv
 
+namespace qsv {
+// A specialised tile-pass kernel (qsv_jit.cpp); fn null = not available for
+// that pass structure (the interpreting kernel runs it).
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+}  // namespace qsv
+
 struct qsv_ctx_s {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -232,6 +241,14 @@ struct qsv_ctx_s {
     bool plan_resident = false;         // d_plan holds the records of memo.passes
     std::vector<qsv::PlanMemo> batch_memo;   // per circuit of the last batch
     qsv::PlanMemo adj_memo;             // passes of the last adjoint sweep's reversed circuit
+
+    // specialised tile-pass kernels (qsv_set_jit): by record-structure hash,
+    // and those of the resident plan (valid while plan_resident)
+    int jit_mode = 0;
+    std::map<uint64_t, qsv::JitKernel> jit_kernels;
+    std::vector<hipFunction_t> jit_plan_fns;
+    double jit_compile_s = 0.0;
+    int jit_compiled = 0;
 };
 
 struct qsv_state_s {
@@ -302,6 +319,16 @@ const std::vector<Pass>& plan_memo(PlanMemo& m, int n, const std::vector<PGate>&
 // if d_plan no longer holds them.
 hipError_t run_passes(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& gates,
                       const std::vector<Pass>& passes, bool cached = false, bool from_zero = false);
+
+// Specialised tile-pass kernels (qsv_jit.cpp).  jit_prepare makes sure each
+// host record in recs (null entries are skipped) has a kernel; fns[i] is
+// null where none could be built.
+bool jit_available();
+uint64_t jit_record_key(int dtype, const char* rec, bool split);
+std::string jit_pass_source(int dtype, const char* rec, bool split, const std::string& fname);
+hipError_t jit_prepare(qsv_ctx ctx, int dtype, const std::vector<const char*>& recs,
+                       const std::vector<bool>& split, std::vector<hipFunction_t>& fns);
+void jit_release(qsv_ctx ctx);
 
 // Reductions.  Stage-1 partials go to ctx scratch; results land in host memory.
 // Z-string sums: out[t] = sum_x |s_x|^2 (-1)^{popcount(x & pmask[t])}, t < nt.

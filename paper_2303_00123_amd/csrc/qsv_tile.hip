@@ -472,8 +472,11 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         bytes += record_bytes_t<R>(passes[i]);
     }
     char* dev = nullptr;
+    const int dt0 = sizeof(R) == 8 ? QSV_C128 : QSV_C64;
+    std::vector<hipFunction_t> jfns;   // specialised kernel of each pass (null: interpret)
     if (bytes && cached && ctx->plan_resident) {
         dev = static_cast<char*>(ctx->d_plan);
+        if (ctx->jit_mode) jfns = ctx->jit_plan_fns;
     } else if (bytes) {
         void* host = nullptr;
         hipError_t e = plan_staging(ctx, bytes, &host);
@@ -482,6 +485,18 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         for (size_t i = 0; i < passes.size(); ++i)
             if (!passes[i].single && !write_record_t<R>(h + offs[i], gates, passes[i]))
                 return hipErrorInvalidValue;
+        if (ctx->jit_mode) {
+            std::vector<const char*> recs(passes.size(), nullptr);
+            std::vector<bool> spl(passes.size(), false);
+            for (size_t i = 0; i < passes.size(); ++i)
+                if (!passes[i].single) {
+                    recs[i] = h + offs[i];
+                    spl[i] = passes[i].split;
+                }
+            e = jit_prepare(ctx, dt0, recs, spl, jfns);
+            if (e != hipSuccess) return e;
+            if (cached) ctx->jit_plan_fns = jfns;
+        }
         void* d = nullptr;
         e = plan_upload(ctx, bytes, &d);
         if (e != hipSuccess) return e;
@@ -505,7 +520,16 @@ hipError_t run_passes_t(qsv_ctx ctx, void* s, int n, const std::vector<PGate>& g
         } else {
             const bool gen = gen_first && i == 0;   // writes the state without reading it
             prof_before(ctx, pname, (gen ? 1.0 : 2.0) * double(uint64_t(1) << n) * sizeof(V));
-            e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, ps.split, dev + offs[i], gen ? 1 : 0);
+            if (i < jfns.size() && jfns[i]) {
+                V* sv = static_cast<V*>(s);
+                const char* pv = dev + offs[i];
+                int fz = gen ? 1 : 0;
+                void* args[] = {&sv, &pv, &fz};
+                e = hipModuleLaunchKernel(jfns[i], unsigned(uint64_t(1) << (n - ps.k)), 1, 1,
+                                          1u << (ps.k - ps.rb), 1, 1, 0, ctx->stream, args, nullptr);
+            } else {
+                e = launch_tile_k<R>(ctx, s, n, ps.k, ps.rb, ps.split, dev + offs[i], gen ? 1 : 0);
+            }
             prof_after(ctx);
         }
         if (e != hipSuccess) return e;

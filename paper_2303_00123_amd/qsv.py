@@ -48,7 +48,7 @@ EXPORTS = [
     "qsv_norm2", "qsv_expect_z", "qsv_inner", "qsv_prob1", "qsv_measure1", "qsv_copy_to_host",
     "qsv_copy_from_host", "qsv_adjoint", "qsv_batch_run", "qsv_profile_begin", "qsv_profile_end",
     "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused", "qsv_applyMC1q", "qsv_applyKq",
-    "qsv_expect_z_dev",
+    "qsv_expect_z_dev", "qsv_set_jit", "qsv_jit_stats", "qsv_jit_source",
 ]
 
 
@@ -92,6 +92,9 @@ def lib():
         "qsv_norm2": [vp, P(d)],
         "qsv_expect_z": [vp, i32, vp, vp, vp, vp],
         "qsv_expect_z_dev": [vp, i32, vp, vp],
+        "qsv_set_jit": [vp, i32],
+        "qsv_jit_stats": [vp, P(i32), P(d)],
+        "qsv_jit_source": [i32, i32, vp, i64, vp, i64, i64, vp, sz, P(sz)],
         "qsv_inner": [vp, vp, vp],
         "qsv_prob1": [vp, i32, P(d)],
         "qsv_measure1": [vp, i32, d, P(i32)],
@@ -193,6 +196,14 @@ class Context:
     def set_tile(self, dtype: int, tile_bits: int = 0, low_bits: int = 0, reg_bits: int = 0,
                  lds_rounds: int = 0):
         self.check(lib().qsv_set_tile(self.handle, dtype, tile_bits, low_bits, reg_bits, lds_rounds))
+
+    def set_jit(self, mode: int):
+        self.check(lib().qsv_set_jit(self.handle, mode))
+
+    def jit_stats(self) -> tuple:
+        k, t = ctypes.c_int(), ctypes.c_double()
+        self.check(lib().qsv_jit_stats(self.handle, ctypes.byref(k), ctypes.byref(t)))
+        return k.value, t.value
 
     def profile_begin(self):
         self.check(lib().qsv_profile_begin(self.handle))
@@ -397,6 +408,23 @@ def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_fused failed")
     return out[: nout.value], pas[: nout.value]
+
+
+def jit_source(n: int, gates, pass_index: int, dtype: int = QSV_C128, params=None) -> str:
+    """Generated source of fused pass `pass_index` (host only)."""
+    g = marshal_gates(gates)
+    p = np.ascontiguousarray(np.zeros(0) if params is None else params, dtype=np.float64)
+    ln = ctypes.c_size_t()
+    st = lib().qsv_jit_source(n, dtype, _ptr(g), len(g), _ptr(p), p.size, pass_index, None, 0,
+                              ctypes.byref(ln))
+    if st != QSV_OK:
+        raise QsvError(st, "qsv_jit_source failed")
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    st = lib().qsv_jit_source(n, dtype, _ptr(g), len(g), _ptr(p), p.size, pass_index, buf,
+                              ln.value + 1, ctypes.byref(ln))
+    if st != QSV_OK:
+        raise QsvError(st, "qsv_jit_source failed")
+    return buf.value.decode()
 
 
 def adjoint(psi: State, lam: State, gates, params, obs, flags: int = FLAG_FORWARD,

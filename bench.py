@@ -11,13 +11,22 @@ Also reported (same JSON line):
                 library's stream over the timed steps: algorithmic flops
                 (FP64 for complex128) and bytes per launch over the average
                 launch time, against MI355X peaks; `bound` is the resource
-                whose time at peak is longer
+                whose time at peak is longer; `traffic` from the committed
+                HBM counter summary while the kernel sources match it
   cpu_baseline  the FP64 CPU oracle on the same 30-qubit circuit, first gates
-                only (time-bounded sample), on this host's cores
-  extras        complex64 throughput of the same circuit; unfused per-gate
-                kernel bandwidth; adjoint-gradient / forward time ratio on a
-                24-qubit ansatz (10 layers RY,RZ + CZ ring, 480 parameters);
-                a 256-circuit batch (12..20 qubits) in one persistent launch
+                only (time-bounded sample), on all of this host's cores
+  extras        the pass kernels used (specialised per pass structure, with
+                their compile time, unless --no-jit or no device compiler);
+                complex64 throughput of the same circuit; the 1000-gate
+                random mix at 30 qubits and random Haar pairs at 32 qubits
+                (64 GiB / 32 GiB) in both precisions, with the flops the fused
+                kernels execute; unfused per-gate kernel bandwidth (c128 and
+                c64 at 30 qubits, c128 at 32); adjoint-gradient / forward time
+                ratio on a 24-qubit ansatz (10 layers RY,RZ + CZ ring, 480
+                parameters) in both precisions; a 256-circuit batch (12..20
+                qubits) in one persistent launch; QFT and a Trotter TFXY chain
+                from 16 to 32 qubits; the CPU oracle on one thread and the
+                host CPU model
 """
 from __future__ import annotations
 
@@ -79,10 +88,12 @@ def run_circuit(q, c, dtype: int, steps: int, warmup: int, jit: bool = False, ob
     ctx.close()
     torch.cuda.empty_cache()
     flops = sum(gate_flops_per_amp(x) for x in c.gates) * float(2 ** n)
+    exec_flops = executed_flops_per_amp(q, c, dtype) * float(2 ** n)
     _, pas = q.plan_fused(n, c.gates, c.params, dtype)
     return {"gates": len(c.gates), "seconds": t1 - t0, "prof": prof, "norm": norm,
             "norm_in_step": float(terms[0]), "terms": [float(x) for x in terms[1:]],
-            "flops_per_step": flops, "warmup_s": t_warm, "jit_kernels": jk, "jit_compile_s": js,
+            "flops_per_step": min(flops, exec_flops), "gate_by_gate_flops_per_step": flops,
+            "warmup_s": t_warm, "jit_kernels": jk, "jit_compile_s": js,
             "passes": int(pas.max()) + 1 if len(pas) else 0}
 
 
@@ -108,6 +119,9 @@ def circuit_extra(q, c, dtype: int, steps: int, warmup: int, jit: bool, label: s
     roof = kernel_roofline(r["prof"], "tile_pass_c64" if c64 else "tile_pass_c128", steps,
                            r["flops_per_step"], "f32" if c64 else "f64")
     if roof is not None:
+        # flops the fused kernels execute; gate by gate (Algs. 1-3) the same
+        # circuit would take this many per launch
+        roof["gate_by_gate_flops_per_launch"] = r["gate_by_gate_flops_per_step"] * steps / roof["launches"]
         out["roofline"] = roof
     return out
 
@@ -131,6 +145,35 @@ def gate_flops_per_amp(gate) -> float:
     if gate.kind == "c1q":
         return 3.0 if diag else 7.0
     return 6.0 if diag else 30.0
+
+
+def executed_flops_per_amp(q, c, dtype: int) -> float:
+    """Real flops per amplitude that the tile kernels execute for circuit c:
+    the fused gate sequence (1-qubit products folded into neighbouring
+    2-qubit gates where that adds no arithmetic), each gate at the cost of
+    the register body that runs it: dense 2x2 14, real 2x2 (RY) 6, diagonal
+    6, controlled dense 7, controlled diagonal 3, dense 4x4 30 (also a
+    controlled gate on control state 0), permutations 0."""
+    import numpy as np
+    recs, _ = q.plan_fused(c.n, c.gates, c.params, dtype)
+    tot = 0.0
+    for r in recs:
+        m = r["m"][0::2] + 1j * r["m"][1::2]
+        d = 4 if r["kind"] == q.qsv.G2Q or (r["kind"] == q.qsv.GC1Q and r["ctrl_state"] == 0) else 2
+        u = m[: d * d].reshape(d, d)
+        perm = np.all((u == 0) | (u == 1)) and np.all(u.sum(axis=0) == 1)
+        diag = np.count_nonzero(u - np.diag(np.diag(u))) == 0
+        if perm:
+            continue
+        if r["kind"] == q.qsv.G1Q:
+            tot += 6.0 if (diag or np.all(u.imag == 0)) else 14.0
+        elif d == 2:
+            tot += 3.0 if diag else 7.0
+        elif r["kind"] == q.qsv.GC1Q:
+            tot += 30.0
+        else:
+            tot += 6.0 if diag else 30.0
+    return tot
 
 
 def kernel_roofline(prof: dict, name: str, steps: int, flops_per_step: float, dtype: str):

@@ -340,9 +340,11 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int
  * default; the environment variable QSV_JIT=1 sets 1 at context creation):
  * the interpreting kernel only.  QSV_ERR_ARG if mode is 1 and no compiler is
  * found (QSV_JIT_CLANG, else $ROCM_PATH/llvm/bin/clang++, else
- * /opt/rocm/llvm/bin/clang++). */
+ * /opt/rocm/llvm/bin/clang++).  If the environment variable QSV_JIT_CACHE
+ * names a directory, accepted kernels are also written there and later
+ * processes load them instead of compiling. */
 qsv_status qsv_set_jit(qsv_ctx ctx, int mode);
-/* Kernels compiled so far on ctx and the wall time spent compiling them. */
+/* Kernels built or loaded so far on ctx and the wall time spent on it. */
 qsv_status qsv_jit_stats(qsv_ctx ctx, int* kernels, double* compile_seconds);
 /* Host-only: the generated source of fused pass `pass` of an n-qubit
  * circuit (n >= 10) planned with the default tile shape for dtype (no device

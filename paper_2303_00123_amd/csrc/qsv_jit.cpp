@@ -318,13 +318,26 @@ hipError_t jit_prepare(qsv_ctx ctx, int dtype, const std::vector<const char*>& r
     for (size_t k = 0; k < todo.size(); ++k) {
         Job& j = jobs[k];
         j.dir = dir;
-        j.name = "qsv_pass_" + std::to_string(k);
+        // one name per structure: traces aggregate the family by its prefix
+        char hex[17];
+        std::snprintf(hex, sizeof(hex), "%016llx", static_cast<unsigned long long>(keys[todo[k]]));
+        j.name = std::string(dtype == QSV_C128 ? "qsv_pass_c128_" : "qsv_pass_c64_") + hex;
         j.src = dir + "/" + j.name + ".hip";
         j.co = dir + "/" + j.name + ".co";
         j.log = dir + "/" + j.name + ".log";
         const std::string text = jit_pass_source(dtype, recs[todo[k]], split[todo[k]], j.name);
         j.ok = !text.empty() && write_file(j.src, text);
     }
+    // persistent cache of accepted kernels (QSV_JIT_CACHE names a directory)
+    std::string cache;
+    if (const char* c = std::getenv("QSV_JIT_CACHE")) cache = c;
+    std::vector<std::string> cached_co(jobs.size());
+    if (!cache.empty())
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            const std::string path = cache + "/" + jobs[k].name + ".co";
+            if (jobs[k].ok && read_file(path, cached_co[k]) && !cached_co[k].empty()) jobs[k].ok = false;
+            else cached_co[k].clear();
+        }
     const std::string clang = compiler_path();
     int par = int(std::thread::hardware_concurrency());
     if (const char* p = std::getenv("QSV_JIT_JOBS")) par = std::atoi(p);
@@ -358,7 +371,14 @@ hipError_t jit_prepare(qsv_ctx ctx, int dtype, const std::vector<const char*>& r
         Job& j = jobs[k];
         JitKernel jk{};
         std::string log, co;
-        if (j.ok && read_file(j.log, log) && resources_ok(log) && read_file(j.co, co)) {
+        const bool from_cache = !cached_co[k].empty();
+        if (from_cache) co.swap(cached_co[k]);
+        if (from_cache || (j.ok && read_file(j.log, log) && resources_ok(log) && read_file(j.co, co))) {
+            if (!from_cache && !cache.empty()) {
+                mkdir(cache.c_str(), 0755);
+                const std::string tmp = cache + "/" + j.name + ".co.tmp" + std::to_string(getpid());
+                if (write_file(tmp, co)) std::rename(tmp.c_str(), (cache + "/" + j.name + ".co").c_str());
+            }
             hipModule_t mod = nullptr;
             hipError_t e = hipModuleLoadData(&mod, co.data());
             if (e == hipSuccess) {

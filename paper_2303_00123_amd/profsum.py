@@ -28,7 +28,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TILE_SOURCES = ["csrc/qsv_tile.hip", "csrc/qsv_tile_core.h", "csrc/qsv_plan.cpp", "csrc/qsv_common.h",
-                "csrc/qsv_internal.h"]
+                "csrc/qsv_internal.h", "csrc/qsv_jit.cpp"]
 
 
 def source_hash(files=TILE_SOURCES) -> str:
@@ -47,11 +47,21 @@ def kernel_stats(path: str):
     return rows
 
 
-def stats_markdown(path: str, cmd: str = "") -> str:
+def stats_markdown(path: str, cmd: str = "", families=()) -> str:
     rows = kernel_stats(path)
     out = []
     if cmd:
         out.append(f"Command: `{cmd}`\n")
+    if families:
+        out.append("| kernel family (name prefix) | kernels | calls | total ms | avg us |")
+        out.append("|---|---|---|---|---|")
+        for fam in families:
+            sel = [r for r in rows if r.get("Name", r.get("KernelName", "")).startswith(fam)]
+            calls = sum(int(float(r.get("Calls", 0))) for r in sel)
+            tot = sum(float(r.get("TotalDurationNs", 0)) for r in sel) / 1e6
+            avg = tot * 1e3 / calls if calls else float("nan")
+            out.append(f"| `{fam}` | {len(sel)} | {calls} | {tot:.3f} | {avg:.1f} |")
+        out.append("")
     out.append("| kernel | calls | total ms | avg us | min us | max us | % |")
     out.append("|---|---|---|---|---|---|---|")
     for r in rows:
@@ -103,6 +113,8 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--cmd", default="")
+    s.add_argument("--family", action="append", default=[],
+                   help="also total the kernels whose name starts with this prefix")
     c = sub.add_parser("counters")
     c.add_argument("--kernel", required=True)
     c.add_argument("--cmd", default="")
@@ -120,7 +132,7 @@ def main(argv=None):
     t.add_argument("--cmd", default="")
     a = ap.parse_args(argv)
     if a.cmd_ == "stats":
-        sys.stdout.write(stats_markdown(a.csv, a.cmd))
+        sys.stdout.write(stats_markdown(a.csv, a.cmd, a.family))
         return
     if a.cmd_ == "counters":
         sys.stdout.write(counters_markdown(a.csv, a.kernel, a.cmd))

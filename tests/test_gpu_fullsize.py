@@ -175,3 +175,42 @@ def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
     st.free()
     print(f"28-qubit brick, complex64: infidelity = {inf:.3e}", flush=True)
     assert inf <= 1e-6
+
+
+def test_config3_28_qubits_full_state_vs_oracle(q):
+    """The Haar-pairs circuit at 28 qubits (10 layers, 420 gates: 2-qubit
+    gates on random pairs across every bit, the planner's hardest case)
+    against the FP64 oracle over the whole state: complex128 with the
+    interpreting and the specialised pass kernels, amplitude by amplitude;
+    complex64 by infidelity."""
+    c = W.layered_haar_pairs(28, 10, 1003)
+    ref = None
+    chunk = 40
+    for k in range(0, len(c.gates), chunk):
+        ref = O.run(W.Circuit(c.n, c.gates[k:k + chunk]), state=ref)
+        print(f"oracle: {min(k + chunk, len(c.gates))}/{len(c.gates)} gates", flush=True)
+    modes = [0, 1]
+    ctx = q.Context()
+    try:
+        ctx.set_jit(1)
+    except q.QsvError:
+        modes = [0]
+    for mode in modes:
+        ctx.set_jit(mode)
+        st = q.State(ctx, c.n)
+        st.init_basis(0)
+        st.apply_circuit(c.gates)
+        err = float(np.max(np.abs(st.to_numpy() - ref)))
+        st.free()
+        print(f"28-qubit Haar pairs, pass kernels {'specialised' if mode else 'interpreting'}: "
+              f"max |d amp| = {err:.3e}", flush=True)
+        assert err <= 1e-12
+    ctx.set_jit(0)
+    st = q.State(ctx, c.n, q.QSV_C64)
+    st.init_basis(0)
+    st.apply_circuit(c.gates)
+    inf = 1.0 - abs(np.vdot(st.to_numpy().astype(np.complex128), ref)) ** 2
+    st.free()
+    ctx.close()
+    print(f"28-qubit Haar pairs, complex64: infidelity = {inf:.3e}", flush=True)
+    assert inf <= 1e-6

@@ -97,3 +97,44 @@ def test_jit_from_zero_new_angles_and_interpreter_agree(q):
     assert np.array_equal(st.to_numpy(), b)
     st.free()
     ctx.close()
+
+
+def test_jit_bench_circuit_equals_interpreter_at_30_qubits(q):
+    """The benchmark's 30-qubit brick circuit in its launch configuration:
+    the specialised pass kernels give the interpreting kernel's amplitudes
+    bit for bit (the interpreting path is checked against the oracle at 28
+    qubits)."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < 40 * 2 ** 30:
+        pytest.skip("needs ~40 GiB of device memory")
+    c = W.layered_cnot_brick(30, 20, seed=3002)
+    ctx = q.Context()
+    a = q.State(ctx, 30, q.QSV_C128)
+    a.apply_circuit(c.gates, flags=q.FLAG_FROM_ZERO)
+    ctx.set_jit(1)
+    b = q.State(ctx, 30, q.QSV_C128)
+    b.apply_circuit(c.gates, flags=q.FLAG_FROM_ZERO)
+    assert torch.equal(a.tensor, b.tensor)
+    a.free()
+    b.free()
+    ctx.close()
+
+
+def test_jit_disk_cache(q, tmp_path, monkeypatch):
+    """With QSV_JIT_CACHE set, a second context loads the kernels the first
+    one compiled (no compile time) and gives the same amplitudes."""
+    monkeypatch.setenv("QSV_JIT_CACHE", str(tmp_path))
+    c = W.layered_haar_pairs(14, 3, seed=840)
+    outs = []
+    for k in range(2):
+        ctx = q.Context()
+        ctx.set_jit(1)
+        outs.append(run(q, ctx, c, q.QSV_C128))
+        kernels, secs = ctx.jit_stats()
+        assert kernels > 0
+        if k == 1:
+            assert secs < 1.0
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert len(list(tmp_path.glob("qsv_pass_c128_*.co"))) > 0

@@ -127,3 +127,50 @@ def test_adjoint_32_qubits_closed_form(dt_name, tol):
         ctx.close()
         del psi, lam
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt_name,n,tol_amp", [("c128", 33, 1e-12), ("c64", 34, 1e-9)])
+def test_unfused_grid_stride_loops_sampled(dt_name, n, tol_amp):
+    """One kernel per gate at 33 (c128) / 34 (c64) qubits, 128 GiB: the pair
+    and quad counts exceed the capped grid, so every gate kernel loops over
+    blocks.  A dense Haar gate on every qubit (Alg. 1), then a controlled
+    gate with its control at index bit n-2 (Alg. 2, half the state moves) on
+    qubits (1, n-2) and a 2-qubit gate (Alg. 3) on (2, n-3).  The two
+    entangled pairs are disjoint, so each sampled amplitude is the oracle's
+    product over the untouched qubits times the oracle's 2-qubit subsystem
+    amplitudes of the two pairs."""
+    import torch
+    import paper_2303_00123_amd as q
+    dt = q.QSV_C128 if dt_name == "c128" else q.QSV_C64
+    _device_or_skip((2 ** n) * (16 if dt == q.QSV_C128 else 8))
+    rng = np.random.default_rng(3300 + n)
+    us = [W.haar_unitary(2, rng) for _ in range(n)]
+    v = W.haar_unitary(2, rng)
+    u2 = W.haar_unitary(4, rng)
+    qstates = np.array([O.apply_1q(O.basis(1), 0, u) for u in us])
+    # subsystems (qubit order within each pair as in the gates)
+    s1 = O.apply_c1q(np.kron(qstates[1], qstates[n - 2]), 0, 1, v, 1)
+    s2 = O.apply_2q(np.kron(qstates[2], qstates[n - 3]), 0, 1, u2)
+    ones = np.array([1.0 + 0j, 1.0 + 0j])
+    rest = qstates.copy()
+    for qb in (1, n - 2, 2, n - 3):
+        rest[qb] = ones
+    ctx = q.Context()
+    st = q.State(ctx, n, dt)
+    try:
+        st.init_basis(0)
+        st.apply_circuit([W.g1(qb, us[qb]) for qb in range(n)], flags=q.FLAG_NO_FUSE)
+        st.applyC1q(1, n - 2, v, ctrl_state=1)
+        st.apply2q(2, n - 3, u2)
+        xs = np.concatenate([[0, 2 ** n - 1, 1, 2 ** (n - 1), 2 ** (n - 2) + 2],
+                             rng.integers(0, 2 ** n, size=40)]).astype(np.int64)
+        got = st.tensor[torch.as_tensor(xs, device="cuda")].cpu().numpy().astype(np.complex128)
+        bit = lambda x, qb: (x >> (n - 1 - qb)) & 1   # noqa: E731
+        ref = np.array([O.product_amplitude(rest, int(x)) * s1[2 * bit(x, 1) + bit(x, n - 2)]
+                        * s2[2 * bit(x, 2) + bit(x, n - 3)] for x in map(int, xs)])
+        assert np.max(np.abs(got - ref)) < tol_amp
+    finally:
+        st.free()
+        ctx.close()
+        del st
+        torch.cuda.empty_cache()

@@ -63,6 +63,7 @@ uint64_t record_key_t(const char* rec, bool split) {
     uint64_t h = 1469598103934665603ull;
     const int32_t tag[3] = {int32_t(sizeof(R)), split ? 1 : 0, 2 /* generator version */};
     h = fnv1a(tag, sizeof(tag), h);
+    if (const char* f = std::getenv("QSV_JIT_CFLAGS")) h = fnv1a(f, std::strlen(f), h);
     h = fnv1a(rec, sizeof(TPassHdr), h);
     h = fnv1a(rec + sizeof(TPassHdr), size_t(ns) * sizeof(TStage), h);
     const TGate<R>* g = reinterpret_cast<const TGate<R>*>(rec + sizeof(TPassHdr) + size_t(ns) * sizeof(TStage));
@@ -255,6 +256,12 @@ pid_t spawn_compile(const std::string& clang, Job& j) {
                                      "--no-gpu-bundle-output", "-O3", "-std=c++17", "-Xclang",
                                      "-target-feature", "-Xclang", "-packed-fp32-ops",
                                      "-Rpass-analysis=kernel-resource-usage", "-I", j.dir, j.src, "-o", j.co};
+    // extra compiler options (QSV_JIT_CFLAGS, whitespace-separated), e.g. a
+    // scheduling strategy to try
+    if (const char* f = std::getenv("QSV_JIT_CFLAGS")) {
+        std::istringstream in(f);
+        for (std::string a; in >> a;) args.insert(args.end() - 2, a);
+    }
     std::vector<char*> argv;
     for (auto& a : args) argv.push_back(const_cast<char*>(a.c_str()));
     argv.push_back(nullptr);

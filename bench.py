@@ -23,7 +23,8 @@ Also reported (same JSON line):
                 kernels execute; unfused per-gate kernel bandwidth (c128 and
                 c64 at 30 qubits, c128 at 32); adjoint-gradient / forward time
                 ratio on a 24-qubit ansatz (10 layers RY,RZ + CZ ring, 480
-                parameters) in both precisions; a 256-circuit batch (12..20
+                parameters) in both precisions; the structured one-pass
+                kernels (diagonal and permutation gates) with their bytes; a 256-circuit batch (12..20
                 qubits) in one persistent launch; QFT and a Trotter TFXY chain
                 from 16 to 32 qubits; the CPU oracle on one thread and the
                 host CPU model
@@ -219,6 +220,45 @@ def measured_traffic(n: int, jit: bool = False):
     if rec.get("source_hash") != profsum.source_hash():
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def structured_sweep(q, W, n: int):
+    """One-pass kernels of structured gates at n qubits (c128): diagonal gates
+    touch only the amplitudes they change (Z, S, T, P: half the state when the
+    qubit's index bit is at or above the 128-byte line; CZ and CP a quarter),
+    permutation gates (X, CNOT, SWAP) only move data.  Bandwidth against the
+    bytes each kernel must move."""
+    import numpy as np
+    import torch
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    T = np.diag([1.0, np.exp(0.25j * np.pi)])
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    SW = np.eye(4, dtype=complex)[[0, 2, 1, 3]]
+    cases = {"diag_z_T": [W.g1(qb, Z if qb % 2 else T) for qb in range(0, n - 3, 3)],
+             "diag_cz": [W.gc(qb, qb + 2, Z) for qb in range(0, n - 6, 4)],
+             "perm_x": [W.g1(qb, X) for qb in range(0, n, 4)],
+             "perm_cnot": [W.cnot(qb, qb + 1) for qb in range(0, n - 4, 4)],
+             "perm_swap": [W.g2(qb, n - 1 - qb, SW) for qb in range(0, n // 2 - 1, 3)]}
+    ctx = q.Context()
+    st = q.State(ctx, n, q.QSV_C128)
+    st.init_basis(0)
+    out = {}
+    for name, gl in cases.items():
+        g = q.marshal_gates(gl)
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        prof = ctx.profile_end()
+        for k, v in prof.items():
+            out[f"{name}:{k}"] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                                  "bytes_per_launch": v["bytes"] / v["launches"],
+                                  "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
+    st.free()
+    del st
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def jit_usable(q) -> bool:
@@ -498,6 +538,8 @@ def main():
         log("extras: unfused sweep")
         extras["unfused_c128"] = unfused_sweep(q, W, args.n)
         extras["unfused_c64"] = unfused_sweep(q, W, args.n, dtype=q.QSV_C64)
+        log("extras: structured one-pass kernels")
+        extras["structured_c128"] = structured_sweep(q, W, args.n)
         if args.n == 30:
             log("extras: unfused sweep at 32 qubits")
             extras["unfused_c128_n32"] = unfused_sweep(q, W, 32, every=4)

@@ -24,7 +24,9 @@ Also reported (same JSON line):
                 c64 at 30 qubits, c128 at 32); adjoint-gradient / forward time
                 ratio on a 24-qubit ansatz (10 layers RY,RZ + CZ ring, 480
                 parameters) in both precisions; the structured one-pass
-                kernels (diagonal and permutation gates) with their bytes; a 256-circuit batch (12..20
+                kernels (diagonal and permutation gates) with their bytes;
+                gates with extra controls and k-qubit gates (one pass each);
+                QFT and Trotter at 30 qubits with the specialised kernels; a 256-circuit batch (12..20
                 qubits) in one persistent launch; QFT and a Trotter TFXY chain
                 from 16 to 32 qubits; the CPU oracle on one thread and the
                 host CPU model
@@ -261,6 +263,55 @@ def structured_sweep(q, W, n: int):
     return out
 
 
+def general_gate_sweep(q, W, n: int):
+    """One-pass kernels of the general gates at n qubits (c128): gates with
+    extra controls (each control halves the amplitudes moved; Toffoli only
+    swaps) and dense gates on k = 3, 4, 5 qubits (8 * 2^k flops per
+    amplitude).  Bandwidth against the bytes each kernel must move; for the
+    k-qubit kernel also its FP64 rate."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(3007)
+    ctx = q.Context()
+    st = q.State(ctx, n, q.QSV_C128)
+    st.init_basis(0)
+    out = {}
+    mc = {"toffoli": [W.toffoli(0, n - 1, 5), W.toffoli(3, 7, n - 2), W.toffoli(n - 5, 1, 9)],
+          "mc3_haar": [W.with_controls(W.g1(4, W.haar_unitary(2, rng)), (0, 10, n - 3)),
+                       W.with_controls(W.g1(n - 6, W.haar_unitary(2, rng)), (2, 12, 20), (1, 0, 1))],
+          "mc1_haar2q": [W.with_controls(W.g2(6, n - 8, W.haar_unitary(4, rng)), (1,))]}
+    for name, gl in mc.items():
+        g = q.marshal_gates(gl)
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        st.apply_circuit(None, marshalled=g, flags=q.FLAG_NO_FUSE)
+        prof = ctx.profile_end()
+        for kname, v in prof.items():
+            out[f"{name}:{kname}"] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                                      "bytes_per_launch": v["bytes"] / v["launches"],
+                                      "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
+    for k in (3, 4, 5):
+        qs = [int(x) for x in rng.choice(n, size=k, replace=False)]
+        u = W.haar_unitary(2 ** k, rng)
+        st.applyKq(qs, u)
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        for _ in range(2):
+            st.applyKq(qs, u)
+        prof = ctx.profile_end()
+        v = prof["kq_c128"]
+        sec = v["ms"] / v["launches"] / 1e3
+        out[f"kq{k}"] = {"qubits": qs, "avg_ms": round(sec * 1e3, 4),
+                         "GB/s": round(v["bytes"] / v["launches"] / sec / 1e9, 1),
+                         "TFLOP/s": round(8 * 2 ** k * 2 ** n / sec / 1e12, 2)}
+    st.free()
+    del st
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def jit_usable(q) -> bool:
     """True if this host has the device compiler the specialised pass kernels need."""
     ctx = q.Context()
@@ -423,6 +474,18 @@ def host_cpu():
             info["physical_cores"] = int(cps) * int(sockets)
     except (OSError, ValueError, subprocess.SubprocessError):
         pass
+    try:   # the kernel's own description (lscpu may print only the family)
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model_cpuinfo"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        info["threads_available"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
     return info
 
 
@@ -540,6 +603,16 @@ def main():
         extras["unfused_c64"] = unfused_sweep(q, W, args.n, dtype=q.QSV_C64)
         log("extras: structured one-pass kernels")
         extras["structured_c128"] = structured_sweep(q, W, args.n)
+        log("extras: multi-controlled and k-qubit gates")
+        extras["general_gates_c128"] = general_gate_sweep(q, W, args.n)
+        if jit:
+            log("extras: QFT and Trotter at 30 qubits, specialised kernels")
+            extras["paper_circuits_specialised"] = {
+                "qft": circuit_extra(q, W.qft(args.n), q.QSV_C128, 2, 1, True,
+                                     f"QFT (Fig. 1), {args.n} qubits, complex128"),
+                "trotter_tfxy_5": circuit_extra(q, W.trotter_tfxy(args.n, 5, 4000 + args.n), q.QSV_C128, 2,
+                                                1, True, f"Trotter TFXY chain, 5 steps, {args.n} qubits, "
+                                                         "complex128")}
         if args.n == 30:
             log("extras: unfused sweep at 32 qubits")
             extras["unfused_c128_n32"] = unfused_sweep(q, W, 32, every=4)

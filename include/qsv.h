@@ -96,8 +96,12 @@ typedef struct qsv_state_s* qsv_state;
  *     P (x) G + (I - P) (x) I,   P = prod_{q in cmask} |v_q><v_q|_q,
  * i.e. G acts only on the amplitudes whose control bits all hold their
  * values (a Toffoli is X on q0 with two extra controls).  cmask = 0: none.
- * Such gates are not fused (each is its own pass over the amplitudes it
- * changes); qsv_batch_run and the rotations of qsv_adjoint reject them. */
+ * In fused circuits a 1-qubit gate with exactly two controls in all (a
+ * QSV_G1Q with two extra controls, or a QSV_GC1Q with one) is rewritten
+ * exactly as five controlled 1-qubit gates (V^2 = U, Barenco et al. 1995)
+ * and fuses like them; any other gate with extra controls runs as a pass of
+ * its own over the amplitudes it changes.  qsv_batch_run and the rotations
+ * of qsv_adjoint reject extra controls. */
 typedef struct {
     int32_t kind;
     int32_t q0, q1;

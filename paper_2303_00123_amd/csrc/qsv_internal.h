@@ -96,7 +96,12 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
 
 // The same fusion over a whole circuit, applied before pass planning when the
 // state is large enough for tile passes (below that, gates run one by one).
+// 1-qubit gates with exactly two controls are first rewritten exactly as
+// two-qubit gates (expand_double_controls) so that they fuse too.
 std::vector<PGate> prefuse(const std::vector<PGate>& gates);
+std::vector<PGate> expand_double_controls(const std::vector<PGate>& gates);
+// A unitary square root of a 2x2 unitary (row-major (re, im) pairs).
+void unitary_sqrt2(const double* u, double* r);
 
 // Device-side gate kinds inside a tile pass.
 enum {

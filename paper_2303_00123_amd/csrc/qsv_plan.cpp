@@ -460,10 +460,104 @@ std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector
     return out;
 }
 
+// A square root of a 2x2 unitary U that is itself unitary: for a 2x2
+// matrix, R = (U + s I) / t with s^2 = det U and t^2 = tr U + 2 s squares
+// to U (Cayley-Hamilton); R is a polynomial in U, so it is normal with
+// unit-modulus eigenvalues, i.e. unitary.  The sign of s is chosen so that
+// t is not zero.
+void unitary_sqrt2(const double* u, double* r) {
+    const cd a(u[0], u[1]), b(u[2], u[3]), c(u[4], u[5]), d(u[6], u[7]);
+    cd s = std::sqrt(a * d - b * c);
+    cd t = std::sqrt(a + d + 2.0 * s);
+    if (std::abs(t) < 1e-8) {
+        s = -s;
+        t = std::sqrt(a + d + 2.0 * s);
+    }
+    const cd m[4] = {(a + s) / t, b / t, c / t, (d + s) / t};
+    for (int i = 0; i < 4; ++i) {
+        r[2 * i] = m[i].real();
+        r[2 * i + 1] = m[i].imag();
+    }
+}
+
+// A 1-qubit gate with exactly two controls (a Toffoli, a doubly-controlled
+// U; Sec. 2.4) becomes the exact two-qubit sequence of Barenco et al. 1995
+// (Lemma 6.1), with V^2 = U:
+//     C_c2(V)_t, CX(c1 -> c2), C_c2(V^dagger)_t, CX(c1 -> c2), C_c1(V)_t
+// (controls on state 0 are wrapped in X on that control).  Its gates then
+// fuse into tile passes like any other; gates with more controls, or with a
+// 2-qubit base, stay barriers that run as passes of their own.
+std::vector<PGate> expand_double_controls(const std::vector<PGate>& gates) {
+    std::vector<PGate> out;
+    out.reserve(gates.size());
+    for (const PGate& g : gates) {
+        int c[2], v[2], nc = 0, t = -1;
+        bool ok = g.cm != 0 && (g.kind == QSV_G1Q || g.kind == QSV_GC1Q);
+        if (ok) {
+            if (g.kind == QSV_GC1Q) {
+                c[nc] = g.p0;
+                v[nc++] = g.cs;
+                t = g.p1;
+            } else {
+                t = g.p0;
+            }
+            for (int p = 0; p < 64 && ok; ++p)
+                if ((g.cm >> p) & 1) {
+                    if (nc == 2) ok = false;
+                    else {
+                        c[nc] = p;
+                        v[nc++] = int((g.cv >> p) & 1);
+                    }
+                }
+            ok = ok && nc == 2;
+        }
+        if (!ok) {
+            out.push_back(g);
+            continue;
+        }
+        static const double X[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+        auto one = [&](int p, const double* m) {
+            PGate x{};
+            x.kind = QSV_G1Q;
+            x.p0 = p;
+            x.cs = 1;
+            std::memcpy(x.m, m, 8 * sizeof(double));
+            out.push_back(x);
+        };
+        auto ctl = [&](int pc, int pt, const double* m) {
+            PGate x{};
+            x.kind = QSV_GC1Q;
+            x.p0 = pc;
+            x.p1 = pt;
+            x.cs = 1;
+            std::memcpy(x.m, m, 8 * sizeof(double));
+            out.push_back(x);
+        };
+        double vm[8], vd[8];
+        unitary_sqrt2(g.m, vm);
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 2; ++k) {
+                vd[2 * (2 * r + k)] = vm[2 * (2 * k + r)];
+                vd[2 * (2 * r + k) + 1] = -vm[2 * (2 * k + r) + 1];
+            }
+        for (int i = 0; i < 2; ++i)
+            if (!v[i]) one(c[i], X);
+        ctl(c[1], t, vm);
+        ctl(c[0], c[1], X);
+        ctl(c[1], t, vd);
+        ctl(c[0], c[1], X);
+        ctl(c[0], t, vm);
+        for (int i = 0; i < 2; ++i)
+            if (!v[i]) one(c[i], X);
+    }
+    return out;
+}
+
 std::vector<PGate> prefuse(const std::vector<PGate>& gates) {
-    std::vector<int> all(gates.size());
-    for (size_t i = 0; i < gates.size(); ++i) all[i] = int(i);
-    return fuse_stage(gates, all);
+    const std::vector<PGate> ex = expand_double_controls(gates);
+    std::vector<int> all(ex.size());
+    for (size_t i = 0; i < ex.size(); ++i) all[i] = int(i);
+    return fuse_stage(ex, all);
 }
 
 void plan_pass_stages(int n, const std::vector<PGate>& gates, Pass& ps) { plan_stages(n, gates, ps); }

@@ -400,11 +400,15 @@ def plan_fused(n: int, gates, params=None, dtype: int = QSV_C128, tile_bits: int
     g = marshal_gates(gates)
     p = np.ascontiguousarray(np.zeros(0) if params is None else params, dtype=np.float64)
     cap = 2 * len(g) + 8
-    out = np.zeros(cap, dtype=GATE_DTYPE)
-    pas = np.zeros(cap, dtype=np.int32)
     nout = ctypes.c_int64()
-    st = lib().qsv_plan_fused(n, dtype, _ptr(g), len(g), _ptr(p), p.size, tile_bits, low_bits,
-                              reg_bits, lds_rounds, _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
+    for _ in range(2):   # a second try with the count the first one reported
+        out = np.zeros(cap, dtype=GATE_DTYPE)
+        pas = np.zeros(cap, dtype=np.int32)
+        st = lib().qsv_plan_fused(n, dtype, _ptr(g), len(g), _ptr(p), p.size, tile_bits, low_bits,
+                                  reg_bits, lds_rounds, _ptr(out), cap, _ptr(pas), ctypes.byref(nout))
+        if st == QSV_OK or nout.value <= cap:
+            break
+        cap = int(nout.value)
     if st != QSV_OK:
         raise QsvError(st, "qsv_plan_fused failed")
     return out[: nout.value], pas[: nout.value]

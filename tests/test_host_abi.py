@@ -189,7 +189,11 @@ def test_fused_sequence_equals_circuit(maker, dtype, tb, lb):
     product equals the circuit: the oracle runs both."""
     c = maker()
     recs, pas = q.plan_fused(c.n, c.gates, c.params, dtype, tb, lb)
-    assert len(recs) <= len(c.gates)
+    # fusion never adds gates; a doubly-controlled gate becomes five, plus X
+    # on each control held at 0, before and after
+    n_dc = sum(1 for g in c.gates if len(getattr(g, "controls", ())) + (g.kind == "c1q") == 2
+               and g.kind in ("1q", "c1q"))
+    assert len(recs) <= len(c.gates) + 8 * n_dc
     assert np.all(np.diff(pas) >= 0)
     phi = W.random_state(c.n, 11)
     got = O.run(_records_to_circuit(c.n, recs), phi)
@@ -256,3 +260,26 @@ def test_device_records_build_for_every_shape(tb, lb, rb, lr):
                 phi = W.random_state(c.n, 3)
                 got = O.run(_records_to_circuit(c.n, recs), phi)
                 assert np.max(np.abs(got - O.run(c, phi))) < 1e-12
+
+
+def test_doubly_controlled_gates_fuse_exactly():
+    """A 1-qubit gate with two controls is rewritten as five controlled
+    gates (Barenco et al.'s construction with V^2 = U) so that it fuses; the
+    fused records equal the gate for matrices where the square root needs
+    its other branch (-I), for X, Z, I, phases and Haar unitaries, and for
+    both control states."""
+    rng = np.random.default_rng(960)
+    mats = [-np.eye(2), np.eye(2), np.array([[0, 1], [1, 0]]), np.diag([1, -1]), np.diag([1, 1j]),
+            np.diag([-1, 1j]), W.haar_unitary(2, rng), W.haar_unitary(2, rng)]
+    n = 12
+    gates = []
+    for k, u in enumerate(mats):
+        t, c0, c1 = (int(x) for x in rng.choice(n, size=3, replace=False))
+        gates.append(W.with_controls(W.g1(t, np.asarray(u, dtype=complex)), (c0, c1), (k & 1, (k >> 1) & 1)))
+        gates.append(W.g1(int(rng.integers(n)), W.haar_unitary(2, rng)))
+    c = W.Circuit(n, gates)
+    recs, pas = q.plan_fused(n, c.gates, c.params, q.QSV_C128)
+    assert not any(int(r["cmask"]) for r in recs)   # nothing left for a pass of its own
+    phi = W.random_state(n, 961)
+    got = O.run(_records_to_circuit(n, recs), phi)
+    assert np.max(np.abs(got - O.run(c, phi))) < 1e-13

@@ -78,7 +78,7 @@ enum {
     QSV_FLAG_NO_FUSE = 1,        /* one kernel per gate (Algs. 1-3 unfused)          */
     QSV_FLAG_FORWARD = 2,        /* qsv_adjoint: run the circuit from |0...0> first  */
     QSV_FLAG_CAPTURE_GRAPH = 4,  /* qsv_batch_run: capture and replay a hipGraph     */
-    QSV_FLAG_TUNE = 8,           /* qsv_batch_run: autotune the tile shape            */
+    QSV_FLAG_TUNE = 8,           /* qsv_batch_run, qsv_apply_circuit: autotune the tile shape */
     QSV_FLAG_FROM_ZERO = 16      /* qsv_apply_circuit: start from |0...0>, see there  */
 };
 
@@ -203,7 +203,15 @@ qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u);
  * QSV_FLAG_FROM_ZERO: the state is first set to |0...0>, as qsv_init_basis
  * with b = 0 would, and the result is the circuit applied to that; when the
  * first pass is a fused one it makes |0...0> in registers instead of reading
- * the state, which saves one write and one read of it. */
+ * the state, which saves one write and one read of it.
+ * QSV_FLAG_TUNE (with QSV_FLAG_FROM_ZERO only): on the first call for a
+ * circuit structure (qubit count, precision, kernel mode, gate kinds, qubits
+ * and controls) run the circuit from |0...0> twice with each candidate tile
+ * shape -- (tile_bits, reg_bits, exchange) = (13, 5, split), (12, 4, split),
+ * (12, 4, full), (12, 3, split), (11, 3, split) -- and keep the shape of the
+ * fastest second run for later calls with the flag on this context; the
+ * state ends as the circuit's result either way.  Calls without the flag
+ * use the context's tile shape (qsv_set_tile). */
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags);
 

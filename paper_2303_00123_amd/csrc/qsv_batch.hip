@@ -232,11 +232,11 @@ void mix(uint64_t& h, uint64_t v) {
     }
 }
 
-// f(0 .. n-1) on up to 16 host threads (work handed out one index at a
-// time); serial for small n.  False if f threw (out of host memory): the
+// f(0 .. n-1) on up to 16 host threads, the context's worker pool and the
+// caller (work handed out one index at a time); serial for small n.  False if f threw (out of host memory): the
 // exception stops at the worker instead of ending the process.
 template <typename F>
-bool parallel_for(int n, F&& f) {
+bool parallel_for(qsv_ctx ctx, int n, F&& f) {
     std::atomic<bool> ok{true};
     auto guarded = [&](int i) {
         try {
@@ -246,25 +246,15 @@ bool parallel_for(int n, F&& f) {
         }
     };
     const unsigned hw = std::thread::hardware_concurrency();
-    const int nt = std::min(std::min(int(hw ? hw : 1), 16), n);
-    if (nt <= 1 || n < 8) {
+    const int nt = std::min(int(hw ? hw : 1), 16);
+    if (nt > 1 && n >= 8 && !ctx->pool) ctx->pool = pool_create(nt - 1);
+    if (nt <= 1 || n < 8 || !ctx->pool) {
         for (int i = 0; i < n; ++i) guarded(i);
         return ok;
     }
-    std::atomic<int> next{0};
-    auto work = [&]() {
-        for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) guarded(i);
-    };
-    std::vector<std::thread> th;
-    th.reserve(size_t(nt - 1));
-    try {
-        for (int t = 1; t < nt; ++t) th.emplace_back(work);
-    } catch (...) {
-        // fewer threads than asked for: the ones started (and this one) finish the work
-    }
-    work();
-    for (std::thread& x : th) x.join();
-    return ok;
+    using G = decltype(guarded);
+    const bool ran = pool_run(ctx->pool, n, [](void* a, int i) { (*static_cast<G*>(a))(i); }, &guarded);
+    return ran && ok;
 }
 
 // A pass of one gate (or none) would run as an unfused kernel in the
@@ -279,7 +269,7 @@ void make_single_stage(Pass& ps, const std::vector<PGate>& gates, int K, bool sp
 
 // Plan every circuit and lay out the device tables.  Returns an error text
 // on invalid input ("" on success).
-std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
+std::string build_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
                         const double* params, int64_t nparams, const int64_t* term_off,
                         const uint64_t* qmasks, const double* w, int dtype, int K, int L,
                         BatchBuild& B, std::vector<PlanMemo>* memo) {
@@ -302,13 +292,16 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
     // 2^13-amplitude tiles (32 per thread) need the split exchange to fit
     // two workgroups per compute unit
     const TileConfig bcfg{K, L, K - 8, coal_bits_for(dtype), K >= 13 ? 1 : 0};
-    const bool built = parallel_for(nb, [&](int c) {
+    const bool built = parallel_for(ctx, nb, [&](int c) {
         const int n = nq[c];
         const int ne = n < K ? K : n;
         const int64_t g0 = gate_off[c], g1 = gate_off[c + 1];
-        std::vector<PGate>& pg = lowered[size_t(c)];
-        pg.reserve(size_t(g1 - g0));
-        uint64_t& h = chash[size_t(c)];
+        // built in locals: the per-circuit slots of `lowered` and `chash` sit
+        // side by side, and writing them per gate from several threads
+        // bounced their cache lines between cores
+        std::vector<PGate> low;
+        low.reserve(size_t(g1 - g0));
+        uint64_t h = chash[size_t(c)];
         for (int64_t i = g0; i < g1; ++i) {
             const qsv_gate& G = g[i];
             PGate p{};
@@ -334,9 +327,11 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
             } else {
                 std::memcpy(p.m, G.m, sizeof(double) * (G.kind == QSV_G2Q ? 32 : 8));
             }
-            pg.push_back(p);
+            low.push_back(p);
         }
-        pg = prefuse(pg);
+        chash[size_t(c)] = h;
+        std::vector<PGate>& pg = lowered[size_t(c)];
+        pg = prefuse(low);
         if (memo) {
             PlanMemo& m = (*memo)[size_t(c)];
             plan_memo(m, ne, pg, bcfg);   // same structure: same plan
@@ -427,6 +422,11 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
     std::stable_sort(order.begin(), order.end(), [&](int a, int b2) {
         return B.circs[size_t(a)].tiles > B.circs[size_t(b2)].tiles;
     });
+    {
+        size_t nitems = 0;
+        for (const BCirc& bc : B.circs) nitems += size_t(bc.npasses) * size_t(bc.tiles);
+        B.items.reserve(nitems);
+    }
     for (int lv = 0; lv < maxp; ++lv)
         for (int c : order) {
             const BCirc& bc = B.circs[size_t(c)];
@@ -441,10 +441,10 @@ std::string build_batch(int nb, const int* nq, const int64_t* gate_off, const qs
 // bytes; each record is cleared first, so padding is deterministic).
 // QSV_ERR_NOMEM if a worker ran out of host memory, QSV_ERR_INTERNAL on a
 // planner inconsistency.
-qsv_status write_batch_records(const BatchBuild& B, char* dst) {
+qsv_status write_batch_records(qsv_ctx ctx, const BatchBuild& B, char* dst) {
     const int nb = int(B.plans.size());
     std::atomic<bool> bad{false};
-    const bool written = parallel_for(nb, [&](int c) {
+    const bool written = parallel_for(ctx, nb, [&](int c) {
         const std::vector<Pass>& pl = *B.plans[size_t(c)];
         for (size_t p = 0; p < pl.size(); ++p) {
             const size_t i = B.rec_first[size_t(c)] + p;
@@ -566,8 +566,10 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
                               const int64_t* term_off, const uint64_t* qmasks, const double* w,
                               int dtype, int K, int L, BatchRun& R, uint64_t& key) {
     BatchBuild B;
-    std::string err = build_batch(nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string err = build_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
                                   K, L, B, &ctx->batch_memo);
+    const auto t1 = std::chrono::steady_clock::now();
     if (!err.empty()) {
         ctx->last_error = "qsv_batch_run: " + err;
         return QSV_ERR_ARG;
@@ -637,7 +639,7 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     ctx->batch_part_off = part_off;
     ctx->batch_state_off = state_off;
     char* h = static_cast<char*>(ctx->h_batch);
-    if (qsv_status ws = write_batch_records(B, h + R.L.plan)) {
+    if (qsv_status ws = write_batch_records(ctx, B, h + R.L.plan)) {
         ctx->last_error = ws == QSV_ERR_NOMEM ? "qsv_batch_run: out of host memory while writing records"
                                               : "qsv_batch_run: internal planner error";
         return ws;
@@ -647,6 +649,12 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     std::memcpy(h + R.L.items, B.items.data(), B.items.size() * sizeof(BItem));
     if (!B.tmask.empty()) std::memcpy(h + R.L.tmask, B.tmask.data(), B.tmask.size() * sizeof(uint64_t));
     if (!B.tw.empty()) std::memcpy(h + R.L.tw, B.tw.data(), B.tw.size() * sizeof(double));
+    if (log_enabled()) {
+        const auto t2 = std::chrono::steady_clock::now();
+        logf("batch staging: build %.2f ms, records and copies %.2f ms",
+             std::chrono::duration<double, std::milli>(t1 - t0).count(),
+             std::chrono::duration<double, std::milli>(t2 - t1).count());
+    }
     return QSV_OK;
 }
 
@@ -669,21 +677,27 @@ static qsv_status finish_batch(qsv_ctx ctx, hipStream_t stream, int nb, double* 
 
 // Key of a batch's shape: qubit counts, gate kinds / qubits / control states /
 // axes and observable masks -- everything but angles, matrices and weights.
+// Words are mixed whole (one multiply each, not one per byte): the key is
+// computed on every call, over every gate of the batch.
 static uint64_t shape_key(int nb, const int* nq, const int64_t* gate_off, const qsv_gate* g,
                           const int64_t* term_off, const uint64_t* qmasks, int dtype) {
     uint64_t h = 1469598103934665603ull;
-    mix(h, uint64_t(nb));
-    mix(h, uint64_t(dtype));
+    auto wmix = [&h](uint64_t v) {
+        h = (h ^ v) * 0x9e3779b97f4a7c15ull;
+        h ^= h >> 29;
+    };
+    wmix(uint64_t(nb));
+    wmix(uint64_t(dtype));
     for (int c = 0; c < nb; ++c) {
-        mix(h, uint64_t(nq[c]));
+        wmix(uint64_t(nq[c]));
         for (int64_t i = gate_off[c]; i < gate_off[c + 1]; ++i) {
             const qsv_gate& G = g[i];
-            mix(h, uint64_t(uint32_t(G.kind)) | (uint64_t(uint32_t(G.q0)) << 8) |
-                       (uint64_t(uint32_t(G.q1)) << 20) | (uint64_t(G.ctrl_state & 1) << 32) |
-                       (uint64_t(G.axis & 3) << 33));
+            wmix(uint64_t(uint32_t(G.kind)) | (uint64_t(uint32_t(G.q0)) << 8) |
+                 (uint64_t(uint32_t(G.q1)) << 20) | (uint64_t(G.ctrl_state & 1) << 32) |
+                 (uint64_t(G.axis & 3) << 33));
         }
-        for (int64_t t = term_off[c]; t < term_off[c + 1]; ++t) mix(h, qmasks[t]);
-        mix(h, 0x5eedull);
+        for (int64_t t = term_off[c]; t < term_off[c + 1]; ++t) wmix(qmasks[t]);
+        wmix(0x5eedull);
     }
     return h;
 }
@@ -701,6 +715,7 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                                     const double* w, int dtype, double* out, int flags) {
     try {
         if (!ctx) return QSV_ERR_ARG;
+        const auto t_entry = std::chrono::steady_clock::now();
         int cur = -1;
         if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
             ctx->last_error = "the context's device is not the current HIP device";
@@ -855,7 +870,15 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                 ctx->last_error = std::string("qsv_batch_run (graph): ") + hipGetErrorString(e);
                 return QSV_ERR_HIP;
             }
-            return finish_batch(ctx, ctx->batch_stream, nb, out);
+            const auto t_launched = std::chrono::steady_clock::now();
+            const qsv_status fs = finish_batch(ctx, ctx->batch_stream, nb, out);
+            if (log_enabled()) {
+                const auto t_done = std::chrono::steady_clock::now();
+                logf("batch call: %.2f ms to launch, %.2f ms waiting and reading results",
+                     std::chrono::duration<double, std::milli>(t_launched - t_entry).count(),
+                     std::chrono::duration<double, std::milli>(t_done - t_launched).count());
+            }
+            return fs;
         }
         e = enqueue_batch(ctx, ctx->stream, dtype, K, nb, R);
         if (e != hipSuccess) {

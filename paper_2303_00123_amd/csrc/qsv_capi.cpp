@@ -324,6 +324,7 @@ qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
         if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
         if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
         jit_release(ctx);
+        pool_destroy(ctx->pool);
         delete ctx;
         return QSV_OK;
     } catch (const std::bad_alloc&) {
@@ -640,6 +641,87 @@ static hipError_t run_fused(qsv_ctx ctx, void* s, int n, int dtype, std::vector<
     return run_passes(ctx, s, n, dtype, ctx->cache_pg, ctx->memo.passes, true, from_zero);
 }
 
+// Structure key of a lowered circuit for the single-state tuner: qubit count,
+// precision, kernel mode and the gates' kinds, positions and controls (not
+// their matrices).
+static uint64_t single_key(const std::vector<PGate>& pg, int n, int dtype, int jit) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(uint64_t(n));
+    mix(uint64_t(dtype) | (uint64_t(jit) << 8));
+    for (const PGate& x : pg) {
+        mix(uint64_t(uint32_t(x.kind)) | (uint64_t(uint32_t(x.p0)) << 8) | (uint64_t(uint32_t(x.p1)) << 16) |
+            (uint64_t(x.cs & 1) << 24));
+        mix(x.cm);
+        mix(x.cv);
+    }
+    return h;
+}
+
+// Tile shapes (tile_bits, reg_bits, split) the single-state tuner tries.
+static const int kSingleShapes[][3] = {{13, 5, 1}, {12, 4, 1}, {12, 4, 0}, {12, 3, 1}, {11, 3, 1}};
+
+// QSV_FLAG_TUNE: run the circuit (from |0...0>) with each candidate tile
+// shape, twice, and keep the shape of the fastest second run for this
+// circuit structure; later calls with the flag reuse it.  Every run is a full
+// application, so the state ends as the circuit's result.
+static hipError_t run_tuned(qsv_ctx ctx, void* s, int n, int dtype, const std::vector<PGate>& pg) {
+    TileConfig& slot = dtype == QSV_C128 ? ctx->tile_c128 : ctx->tile_c64;
+    const TileConfig saved = slot;
+    const uint64_t key = single_key(pg, n, dtype, ctx->jit_mode);
+    auto it = ctx->tuned_single.find(key);
+    hipError_t e = hipSuccess;
+    if (it != ctx->tuned_single.end()) {
+        slot = it->second;
+        e = run_fused(ctx, s, n, dtype, std::vector<PGate>(pg), true);
+        slot = saved;
+        return e;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    float best = 1e30f;
+    TileConfig bestc = saved;
+    int tried = 0;
+    for (const auto& sh : kSingleShapes) {
+        if (sh[0] > n || !tile_shape_supported(dtype, sh[0], sh[1])) continue;
+        slot = TileConfig{sh[0], coal_bits_for(dtype), sh[1], coal_bits_for(dtype), sh[2]};
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, ctx->stream);
+            if (e == hipSuccess) e = run_fused(ctx, s, n, dtype, std::vector<PGate>(pg), true);
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess && rep == 1 && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t;
+        }
+        if (e != hipSuccess) break;
+        ++tried;
+        logf("tune: n=%d tile 2^%d, %d register bits, %s exchange: %.3f ms", n, sh[0], sh[1],
+             sh[2] ? "split" : "full", ms);
+        if (ms < best) {
+            best = ms;
+            bestc = slot;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    slot = saved;
+    // no candidate fits (fewer qubits than the smallest candidate tile): the
+    // context's own shape, which the planner clamps to the qubit count
+    if (e == hipSuccess && tried == 0) e = run_fused(ctx, s, n, dtype, std::vector<PGate>(pg), true);
+    if (e == hipSuccess) ctx->tuned_single[key] = bestc;
+    return e;
+}
+
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags) {
     try {
@@ -647,7 +729,11 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
         qsv_ctx ctx = st->ctx;
         if (ng < 0 || (ng > 0 && !g)) return fail(ctx, QSV_ERR_ARG, "bad gate list");
         if (nparams < 0) return fail(ctx, QSV_ERR_ARG, "negative parameter count");
-        if (flags & ~(QSV_FLAG_NO_FUSE | QSV_FLAG_FROM_ZERO)) return fail(ctx, QSV_ERR_ARG, "unknown flag");
+        if (flags & ~(QSV_FLAG_NO_FUSE | QSV_FLAG_FROM_ZERO | QSV_FLAG_TUNE))
+            return fail(ctx, QSV_ERR_ARG, "unknown flag");
+        if ((flags & QSV_FLAG_TUNE) && !(flags & QSV_FLAG_FROM_ZERO))
+            return fail(ctx, QSV_ERR_ARG, "QSV_FLAG_TUNE needs QSV_FLAG_FROM_ZERO (each candidate reruns "
+                                          "the circuit from |0...0>)");
         std::vector<PGate> pg;
         if (qsv_status s = lower(ctx, st->n, g, ng, params, nparams, pg)) return s;
         const bool from_zero = (flags & QSV_FLAG_FROM_ZERO) != 0;
@@ -657,6 +743,10 @@ qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const 
         if (flags & QSV_FLAG_NO_FUSE) {
             for (const PGate& x : pg)
                 HIP_OR_FAIL(ctx, launch_gate(ctx, st->ptr, st->n, st->dtype, x), "gate launch");
+            return QSV_OK;
+        }
+        if ((flags & QSV_FLAG_TUNE) && st->n >= kMinTileBits) {
+            HIP_OR_FAIL(ctx, run_tuned(ctx, st->ptr, st->n, st->dtype, pg), "tuned tile passes");
             return QSV_OK;
         }
         HIP_OR_FAIL(ctx, run_fused(ctx, st->ptr, st->n, st->dtype, std::move(pg), from_zero), "tile passes");

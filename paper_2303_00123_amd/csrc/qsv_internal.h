@@ -183,6 +183,14 @@ struct PlanMemo {
 }  // namespace qsv
 
 namespace qsv {
+// Host worker threads that run f(arg, i) for i in [0, n) together with the
+// calling thread (qsv_pool.cpp).  pool_run returns false if a call threw;
+// one caller at a time per pool.
+class WorkerPool;
+WorkerPool* pool_create(int workers);   // nullptr if no thread could be started
+void pool_destroy(WorkerPool* p);
+bool pool_run(WorkerPool* p, int n, void (*f)(void*, int), void* arg);
+
 // A specialised tile-pass kernel (qsv_jit.cpp); fn null = not available for
 // that pass structure (the interpreting kernel runs it).
 struct JitKernel {
@@ -246,6 +254,13 @@ struct qsv_ctx_s {
     bool plan_resident = false;         // d_plan holds the records of memo.passes
     std::vector<qsv::PlanMemo> batch_memo;   // per circuit of the last batch
     qsv::PlanMemo adj_memo;             // passes of the last adjoint sweep's reversed circuit
+
+    // single-state tuner (QSV_FLAG_TUNE on qsv_apply_circuit): circuit
+    // structure key -> chosen tile shape
+    std::map<uint64_t, qsv::TileConfig> tuned_single;
+
+    // host worker threads of the batch planner (started on first use)
+    qsv::WorkerPool* pool = nullptr;
 
     // specialised tile-pass kernels (qsv_set_jit): by record-structure hash,
     // and those of the resident plan (valid while plan_resident)

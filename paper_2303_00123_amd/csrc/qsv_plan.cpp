@@ -330,6 +330,7 @@ static int cost1(const cd* u) { return (u[1] == 0.0 && u[2] == 0.0) ? 4 : 8; }
 
 std::vector<PGate> fuse_stage(const std::vector<PGate>& gates, const std::vector<int>& idx) {
     std::vector<PGate> out;
+    out.reserve(idx.size());   // fusion never adds gates
     bool has[64] = {false};
     cd pend[64][4];
     // index in `out` of the last emitted gate touching each position (-1: none)
@@ -554,10 +555,14 @@ std::vector<PGate> expand_double_controls(const std::vector<PGate>& gates) {
 }
 
 std::vector<PGate> prefuse(const std::vector<PGate>& gates) {
-    const std::vector<PGate> ex = expand_double_controls(gates);
-    std::vector<int> all(ex.size());
-    for (size_t i = 0; i < ex.size(); ++i) all[i] = int(i);
-    return fuse_stage(ex, all);
+    bool any_cm = false;
+    for (const PGate& g : gates) any_cm |= g.cm != 0;
+    std::vector<PGate> ex;
+    if (any_cm) ex = expand_double_controls(gates);
+    const std::vector<PGate>& src = any_cm ? ex : gates;
+    std::vector<int> all(src.size());
+    for (size_t i = 0; i < src.size(); ++i) all[i] = int(i);
+    return fuse_stage(src, all);
 }
 
 void plan_pass_stages(int n, const std::vector<PGate>& gates, Pass& ps) { plan_stages(n, gates, ps); }

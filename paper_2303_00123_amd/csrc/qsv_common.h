@@ -22,6 +22,32 @@ inline unsigned capped_grid(uint64_t blocks) {
     return unsigned(blocks < 1 ? 1 : (blocks > kMaxGridBlocks ? kMaxGridBlocks : blocks));
 }
 
+// Order in which a grid-stride kernel visits its nblk logical blocks.  The
+// chip dispatches workgroups to its 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8).  In XCD order the workgroups of one XCD take one contiguous
+// eighth of the blocks, in steps of gridDim/8, so at any moment each XCD
+// streams its own region of the state rather than all eight interleaving
+// on the same lines and DRAM pages: at 32 qubits this raised a controlled
+// gate from 5.1-5.3 to 6.2-6.5 TB/s.  It needs nblk and gridDim.x to be
+// multiples of 8; otherwise the blocks are visited in plain order.
+struct BlockWalk {
+    uint64_t first, end, step;
+    __device__ __forceinline__ explicit BlockWalk(uint64_t nblk) {
+        const uint64_t G = gridDim.x;
+        if ((nblk & 7) == 0 && (G & 7) == 0) {
+            const uint64_t e = nblk >> 3, x = blockIdx.x & 7u;
+            first = x * e + (blockIdx.x >> 3);
+            end = x * e + e;
+            step = G >> 3;
+        } else {
+            first = blockIdx.x;
+            end = nblk;
+            step = G;
+        }
+    }
+};
+inline __device__ __forceinline__ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
 template <typename R>
 struct M2 { R v[8]; };   // 2x2 row-major (re, im)
 template <typename R>

@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kThreads) void k_apply1q(typename V2T<R>::type* __r
     using V = typename V2T<R>::type;
     constexpr int P = GatePairs<R>::value;
     constexpr uint64_t BS = uint64_t(kThreads) * P;
-    for (uint64_t blk = blockIdx.x; blk * BS < npairs; blk += gridDim.x) {
+    const BlockWalk bw(ceil_div(npairs, BS));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
         const uint64_t j0 = blk * BS + threadIdx.x;
         const uint64_t w = uint64_t(1) << p;
         V a[P], b[P];
@@ -138,7 +139,8 @@ __global__ __launch_bounds__(kThreads) void k_applyc1q(typename V2T<R>::type* __
     using V = typename V2T<R>::type;
     constexpr int P = GatePairs<R>::value;
     constexpr uint64_t BS = uint64_t(kThreads) * P;
-    for (uint64_t blk = blockIdx.x; blk * BS < npairs; blk += gridDim.x) {
+    const BlockWalk bw(ceil_div(npairs, BS));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
         const uint64_t j0 = blk * BS + threadIdx.x;
         const uint64_t wt = uint64_t(1) << pt;
         const uint64_t wc = cs ? (uint64_t(1) << pc) : 0;
@@ -176,7 +178,8 @@ __global__ __launch_bounds__(kThreads) void k_apply2q(typename V2T<R>::type* __r
     using V = typename V2T<R>::type;
     constexpr int P = GateQuads<R>::value;
     constexpr uint64_t BS = uint64_t(kThreads) * P;
-    for (uint64_t blk = blockIdx.x; blk * BS < nquads; blk += gridDim.x) {
+    const BlockWalk bw(ceil_div(nquads, BS));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
         const uint64_t j0 = blk * BS + threadIdx.x;
         const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
         V v[P][4];
@@ -227,7 +230,8 @@ __global__ __launch_bounds__(kThreads) void k_diag(typename V2T<R>::type* __rest
     using V = typename V2T<R>::type;
     constexpr int P = PPT<R>::value;
     constexpr uint64_t BS = uint64_t(kThreads) * P;
-    for (uint64_t blk = blockIdx.x; blk * BS < items; blk += gridDim.x) {
+    const BlockWalk bw(ceil_div(items, BS));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
         const uint64_t j0 = blk * BS + threadIdx.x;
         V a[P];
         uint64_t xs[P];
@@ -266,8 +270,10 @@ __global__ __launch_bounds__(kThreads) void k_perm2q(typename V2T<R>::type* __re
     using V = typename V2T<R>::type;
     const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
     const uint64_t off[4] = {0, wb, wa, wa + wb};
-    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < nquads;
-         j += uint64_t(gridDim.x) * kThreads) {
+    const BlockWalk bw(ceil_div(nquads, kThreads));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
+        const uint64_t j = blk * kThreads + threadIdx.x;
+        if (j >= nquads) continue;
         const uint64_t i0 = insert0(insert0(j, plo), phi);
         V v[4];
 #pragma unroll
@@ -294,8 +300,10 @@ __global__ __launch_bounds__(kThreads) void k_mc(typename V2T<R>::type* __restri
                                                  int pa, int pb, M4<R> u) {
     using V = typename V2T<R>::type;
     const uint64_t wa = uint64_t(1) << pa, wb = uint64_t(1) << pb;
-    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < items;
-         j += uint64_t(gridDim.x) * kThreads) {
+    const BlockWalk bw(ceil_div(items, kThreads));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
+        const uint64_t j = blk * kThreads + threadIdx.x;
+        if (j >= items) continue;
         uint64_t x = j;
         for (int i = 0; i < npos; ++i) x = insert0(x, ip.p[i]);
         x |= fix;
@@ -337,8 +345,10 @@ __global__ __launch_bounds__(kThreads) void k_kq(typename V2T<R>::type* __restri
                                                  const R* __restrict__ u) {
     using V = typename V2T<R>::type;
     constexpr int D = 1 << K;
-    for (uint64_t j = uint64_t(blockIdx.x) * kThreads + threadIdx.x; j < items;
-         j += uint64_t(gridDim.x) * kThreads) {
+    const BlockWalk bw(ceil_div(items, kThreads));
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
+        const uint64_t j = blk * kThreads + threadIdx.x;
+        if (j >= items) continue;
         uint64_t x = j;
 #pragma unroll
         for (int i = 0; i < K; ++i) x = insert0(x, ip.p[i]);

@@ -538,6 +538,9 @@ def main():
                          "metric is defined on complex128)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of 2^k complex128 amplitudes (counter calibration)")
+    ap.add_argument("--unfused-only", action="store_true",
+                    help="only run the one-kernel-per-gate sweeps (30 qubits in both precisions, "
+                         "32 qubits complex128) and print their bandwidths (profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the path runs on one MI355X per process; --gpus must be 1 "
@@ -559,6 +562,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 16, "copies": 3}))
+        return
+
+    if args.unfused_only:
+        out = {"unfused_c128": unfused_sweep(q, W, 30),
+               "unfused_c64": unfused_sweep(q, W, 30, dtype=q.QSV_C64),
+               "unfused_c128_n32": unfused_sweep(q, W, 32, every=4)}
+        print(json.dumps(out), flush=True)
         return
 
     jit = not args.no_jit and jit_usable(q)

@@ -107,6 +107,28 @@ def counters_markdown(paths, kernel_substr: str, cmd: str = "") -> str:
     return "\n".join(out) + "\n"
 
 
+def dispatches_markdown(path: str, cmd: str = "", prefix: str = "") -> str:
+    """Per (kernel, grid size) duration statistics from a rocprofv3
+    kernel_trace CSV: one kernel launched on different state sizes shows as
+    one row per size."""
+    groups = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
+            if prefix and prefix not in name:
+                continue
+            key = (name, int(r["Grid_Size_X"]))
+            groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = []
+    if cmd:
+        out.append(f"Command: `{cmd}`\n")
+    out.append("| kernel | grid (work-items) | calls | avg us | min us | max us |")
+    out.append("|---|---|---|---|---|---|")
+    for (name, grid), d in sorted(groups.items(), key=lambda kv: (-sum(kv[1]), kv[0])):
+        out.append(f"| `{name[:90]}` | {grid} | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_", required=True)
@@ -119,6 +141,10 @@ def main(argv=None):
     c.add_argument("--kernel", required=True)
     c.add_argument("--cmd", default="")
     c.add_argument("csv", nargs="+")
+    d = sub.add_parser("dispatches")
+    d.add_argument("csv")
+    d.add_argument("--cmd", default="")
+    d.add_argument("--kernel", default="", help="only kernels whose name contains this")
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
     t.add_argument("--fetch", required=True)
@@ -133,6 +159,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd_ == "stats":
         sys.stdout.write(stats_markdown(a.csv, a.cmd, a.family))
+        return
+    if a.cmd_ == "dispatches":
+        sys.stdout.write(dispatches_markdown(a.csv, a.cmd, a.kernel))
         return
     if a.cmd_ == "counters":
         sys.stdout.write(counters_markdown(a.csv, a.kernel, a.cmd))

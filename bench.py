@@ -264,11 +264,12 @@ def structured_sweep(q, W, n: int):
 
 
 def general_gate_sweep(q, W, n: int):
-    """One-pass kernels of the general gates at n qubits (c128): gates with
-    extra controls (each control halves the amplitudes moved; Toffoli only
+    """One-pass kernels of the general gates at n qubits: gates with extra
+    controls (c128; each control halves the amplitudes moved; Toffoli only
     swaps) and dense gates on k = 3, 4, 5 qubits (8 * 2^k flops per
-    amplitude).  Bandwidth against the bytes each kernel must move; for the
-    k-qubit kernel also its FP64 rate."""
+    amplitude) on the matrix cores and on the vector units, both
+    precisions.  Bandwidth against the bytes each kernel must move; for the
+    k-qubit kernels also their flop rate."""
     import numpy as np
     import torch
     rng = np.random.default_rng(3007)
@@ -291,24 +292,39 @@ def general_gate_sweep(q, W, n: int):
             out[f"{name}:{kname}"] = {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
                                       "bytes_per_launch": v["bytes"] / v["launches"],
                                       "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)}
-    for k in (3, 4, 5):
-        qs = [int(x) for x in rng.choice(n, size=k, replace=False)]
-        u = W.haar_unitary(2 ** k, rng)
-        st.applyKq(qs, u)
-        torch.cuda.synchronize()
-        ctx.profile_begin()
-        for _ in range(2):
-            st.applyKq(qs, u)
-        prof = ctx.profile_end()
-        v = prof["kq_c128"]
-        sec = v["ms"] / v["launches"] / 1e3
-        out[f"kq{k}"] = {"qubits": qs, "avg_ms": round(sec * 1e3, 4),
-                         "GB/s": round(v["bytes"] / v["launches"] / sec / 1e9, 1),
-                         "TFLOP/s": round(8 * 2 ** k * 2 ** n / sec / 1e12, 2)}
     st.free()
     del st
     ctx.close()
     torch.cuda.empty_cache()
+    # dense k-qubit gates: matrix cores (FP64 MFMA for complex128, FP32 for
+    # complex64; mode 2, so also k = 4, which the default leaves on the
+    # vector units) against the vector-unit kernel, same qubits and matrix
+    for k in (3, 4, 5):
+        qs = [int(x) for x in rng.choice(n, size=k, replace=False)]
+        u = W.haar_unitary(2 ** k, rng)
+        for dtype, tag in ((q.QSV_C128, "c128"), (q.QSV_C64, "c64")):
+            for mode, kname in ((2, "kq_mfma"), (0, "kq")):
+                ctx = q.Context()
+                ctx.set_matrix_cores(mode)
+                st = q.State(ctx, n, dtype)
+                st.init_basis(0)
+                st.applyKq(qs, u)
+                torch.cuda.synchronize()
+                ctx.profile_begin()
+                for _ in range(2):
+                    st.applyKq(qs, u)
+                prof = ctx.profile_end()
+                v = prof[f"{kname}_{tag}"]
+                sec = v["ms"] / v["launches"] / 1e3
+                label = f"kq{k}_{tag}" + ("_matrix_cores" if mode else "_vector")
+                out[label] = {"qubits": qs, "avg_ms": round(sec * 1e3, 4),
+                              "GB/s": round(v["bytes"] / v["launches"] / sec / 1e9, 1),
+                              ("TFLOP/s (FP64)" if tag == "c128" else "TFLOP/s (FP32)"):
+                                  round(8 * 2 ** k * 2 ** n / sec / 1e12, 2)}
+                st.free()
+                del st
+                ctx.close()
+                torch.cuda.empty_cache()
     return out
 
 
@@ -538,6 +554,9 @@ def main():
                          "metric is defined on complex128)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of 2^k complex128 amplitudes (counter calibration)")
+    ap.add_argument("--general-only", action="store_true",
+                    help="only run the sweep of multi-controlled and dense k-qubit gates (matrix cores "
+                         "and vector units) at 30 qubits and print it (profiling aid)")
     ap.add_argument("--unfused-only", action="store_true",
                     help="only run the one-kernel-per-gate sweeps (30 qubits in both precisions, "
                          "32 qubits complex128) and print their bandwidths (profiling aid)")
@@ -562,6 +581,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 16, "copies": 3}))
+        return
+
+    if args.general_only:
+        print(json.dumps({"general_gates": general_gate_sweep(q, W, 30)}), flush=True)
         return
 
     if args.unfused_only:

@@ -192,7 +192,8 @@ qsv_status qsv_applyMC1q(qsv_state st, int nctrl, const int* controls, const int
  * rows/columns indexed by sum_i x_{qubits[i]} 2^(k-1-i): qubits[0] is the
  * most significant bit of the local index, which is eq. (1)'s order when
  * the qubits are contiguous and ascending.  1 <= k <= 5, k <= n.  The matrix
- * is copied to device memory before the call returns. */
+ * is copied to device memory before the call returns.  For k >= 3 the
+ * context's matrix-core setting (qsv_set_matrix_cores) picks the kernel. */
 qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u);
 
 /* Apply gates g[0..ng) in order.  Rotations read params[0..nparams).  By
@@ -356,6 +357,15 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int
  * names a directory, accepted kernels are also written there and later
  * processes load them instead of compiling. */
 qsv_status qsv_set_jit(qsv_ctx ctx, int mode);
+/* Matrix cores for dense k-qubit gates (qsv_applyKq with n - k >= 6): U
+ * is applied as real matrix products on the MFMA units, FP64 MFMA for
+ * complex128 and FP32 MFMA for complex64 (full precision; only the
+ * summation order differs from the vector kernel), 16 groups of 2^k
+ * amplitudes per wave.  mode 1 (the default): for k = 3 and 5, where they
+ * measured faster than the vector units; mode 2: for every k in 3..5; mode
+ * 0: never (the vector kernel, one output row at a time).  Other gates and
+ * the fused passes are not affected.  QSV_ERR_ARG for another mode. */
+qsv_status qsv_set_matrix_cores(qsv_ctx ctx, int mode);
 /* Kernels built or loaded so far on ctx and the wall time spent on it. */
 qsv_status qsv_jit_stats(qsv_ctx ctx, int* kernels, double* compile_seconds);
 /* Host-only: the generated source of fused pass `pass` of an n-qubit

@@ -571,18 +571,25 @@ qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u) 
             seen |= uint64_t(1) << qubits[i];
             pos[i] = pos_of(n, qubits[i]);
         }
-        // the matrix in the state's real type, through the plan staging buffer
-        const size_t vals = size_t(2) << (2 * k);
+        // the matrix in the state's real type, through the plan staging
+        // buffer: as given for the vector kernel, as the real 2^(k+1) square
+        // block matrix in lane order for the matrix cores
+        const bool mfma = kq_mfma_applies(n, k, ctx->kq_mfma);
+        const size_t vals = mfma ? size_t(4) << (2 * k) : size_t(2) << (2 * k);
         const size_t rs = st->dtype == QSV_C128 ? sizeof(double) : sizeof(float);
         void* host = nullptr;
         HIP_OR_FAIL(ctx, plan_staging(ctx, vals * rs, &host), "applyKq staging");
-        for (size_t i = 0; i < vals; ++i) {
-            if (st->dtype == QSV_C128) static_cast<double*>(host)[i] = u[i];
-            else static_cast<float*>(host)[i] = float(u[i]);
+        if (mfma) {
+            kq_mfma_pack(st->dtype, k, u, host);
+        } else {
+            for (size_t i = 0; i < vals; ++i) {
+                if (st->dtype == QSV_C128) static_cast<double*>(host)[i] = u[i];
+                else static_cast<float*>(host)[i] = float(u[i]);
+            }
         }
         void* dev = nullptr;
         HIP_OR_FAIL(ctx, plan_upload(ctx, vals * rs, &dev), "applyKq upload");
-        HIP_OR_FAIL(ctx, launch_kq(ctx, st->ptr, n, st->dtype, k, pos, dev), "applyKq");
+        HIP_OR_FAIL(ctx, launch_kq(ctx, st->ptr, n, st->dtype, k, pos, dev, mfma), "applyKq");
         return QSV_OK;
     } catch (const std::bad_alloc&) {
         return QSV_ERR_NOMEM;
@@ -1038,6 +1045,13 @@ qsv_status qsv_set_tile(qsv_ctx ctx, int dtype, int tile_bits, int low_bits, int
     } catch (...) {
         return QSV_ERR_INTERNAL;
     }
+}
+
+qsv_status qsv_set_matrix_cores(qsv_ctx ctx, int mode) {
+    if (!ctx) return QSV_ERR_ARG;
+    if (mode < 0 || mode > 2) return fail(ctx, QSV_ERR_ARG, "matrix-core mode must be 0, 1 or 2");
+    ctx->kq_mfma = mode;
+    return QSV_OK;
 }
 
 qsv_status qsv_set_jit(qsv_ctx ctx, int mode) {

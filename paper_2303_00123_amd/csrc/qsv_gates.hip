@@ -371,6 +371,94 @@ __global__ __launch_bounds__(kThreads) void k_kq(typename V2T<R>::type* __restri
     }
 }
 
+// ------------------------------- dense k-qubit block on the matrix cores
+// The gate of k_kq as real matrix products: with amplitudes split into
+// (re, im), y = U x is a real product of the 2D x 2D matrix
+// [[Re U, -Im U], [Im U, Re U]] (rows and columns interleaved per
+// amplitude) with 2D x 16 real columns, 16 groups per wave.  One 16x16x4
+// MFMA adds the product of a 16 x 4 slice of the matrix with a 4 x 16
+// slice of the columns; D/2 of them give 16 output rows (8 amplitudes) of
+// the 16 groups.  Lane l (group j = l mod 16, quarter q = l / 16) loads
+// input amplitude 4m + q of its group whole and feeds its real part to
+// slice 2m and its imaginary part to slice 2m + 1; it ends with amplitudes
+// 8*rc + 2q and 8*rc + 2q + 1 of its group, both parts, for output slice
+// rc.  The D/8 output slices accumulate side by side (independent chains
+// for the matrix pipeline).  The host stores the matrix pre-arranged in
+// this lane order (kq_mfma_pack), so the value a lane feeds to each
+// product sits at a fixed index.  FP64 MFMA for complex128, FP32 MFMA for complex64: full
+// precision, only the summation order differs from k_kq.  Needs 2^(n-K)
+// to be a multiple of 64 (four waves of 16 groups per workgroup).
+template <typename R>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaOp<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_kq_mfma(typename V2T<R>::type* __restrict__ s,
+                                                      uint64_t items, InsPos ip, KOff<K> off,
+                                                      const R* __restrict__ apack) {
+    using V = typename V2T<R>::type;
+    using Acc = typename MfmaOp<R>::acc;
+    constexpr int D = 1 << K;
+    constexpr int NKC = D / 2;   // 4-row input slices
+    constexpr int NRC = D / 8;   // 16-row output slices
+    const int lane = int(threadIdx.x & 63u);
+    const int wave = int(threadIdx.x >> 6);
+    const int j = lane & 15, qq = lane >> 4;
+    // the matrix in LDS, read at each product: held in registers (D^2/16 per
+    // lane) it cost occupancy and measured slower for k = 4, 5
+    __shared__ R alds[4 * D * D];
+    for (int i = int(threadIdx.x); i < 4 * D * D; i += kThreads) alds[i] = apack[i];
+    __syncthreads();
+    const BlockWalk bw(items / 64);
+    for (uint64_t blk = bw.first; blk < bw.end; blk += bw.step) {
+        // keeps the LDS reads inside the loop (hoisted out of it, they would
+        // hold every matrix value in registers again)
+        asm volatile("" ::: "memory");
+        uint64_t x = blk * 64 + uint64_t(wave) * 16 + uint64_t(j);
+#pragma unroll
+        for (int i = 0; i < K; ++i) x = insert0(x, ip.p[i]);
+        R b[NKC];
+#pragma unroll
+        for (int m = 0; m < NKC / 2; ++m) {
+            const V v = ld_nt(s + x + off.o[4 * m + qq]);
+            b[2 * m] = v.x;
+            b[2 * m + 1] = v.y;
+        }
+        Acc c[NRC];
+#pragma unroll
+        for (int rc = 0; rc < NRC; ++rc) c[rc] = Acc{R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+            for (int rc = 0; rc < NRC; ++rc)
+                c[rc] = MfmaOp<R>::mma(alds[(rc * NKC + kc) * 64 + lane], b[kc], c[rc]);
+#pragma unroll
+        for (int rc = 0; rc < NRC; ++rc) {
+            const int c0 = 8 * rc + 2 * qq;
+            V o0, o1;
+            o0.x = c[rc][0];
+            o0.y = c[rc][1];
+            o1.x = c[rc][2];
+            o1.y = c[rc][3];
+            st_nt(s + x + off.o[c0], o0);
+            st_nt(s + x + off.o[c0 + 1], o1);
+        }
+    }
+}
+
 template <typename R>
 unsigned grid_for(uint64_t items, int per_thread) {
     const uint64_t per_block = uint64_t(kThreads) * per_thread;
@@ -621,7 +709,7 @@ hipError_t mc_t(qsv_ctx ctx, void* s, int n, const PGate& g) {
 // k-qubit gate: positions pos[i] of the caller's qubits (pos[0] = most
 // significant local bit), U already in device memory in the state's type.
 template <typename R, int K>
-hipError_t kq_launch(qsv_ctx ctx, void* s, int n, const int* pos, const void* du) {
+hipError_t kq_launch(qsv_ctx ctx, void* s, int n, const int* pos, const void* du, bool mfma) {
     using V = typename V2T<R>::type;
     InsPos ip{};
     int sorted[K];
@@ -637,6 +725,19 @@ hipError_t kq_launch(qsv_ctx ctx, void* s, int n, const int* pos, const void* du
         off.o[c] = o;
     }
     const uint64_t items = uint64_t(1) << (n - K);
+    if constexpr (K >= 3) {
+        if (mfma) {
+            if (items % 64 != 0) return hipErrorInvalidValue;   // the caller checks kq_mfma_applies
+            prof_before(ctx, sizeof(R) == 8 ? "kq_mfma_c128" : "kq_mfma_c64",
+                        2.0 * double(uint64_t(1) << n) * sizeof(V));
+            hipLaunchKernelGGL((k_kq_mfma<R, K>), dim3(capped_grid(items / 64)), dim3(kThreads), 0, ctx->stream,
+                               static_cast<V*>(s), items, ip, off, static_cast<const R*>(du));
+            const hipError_t e = hipGetLastError();
+            prof_after(ctx);
+            return e;
+        }
+    }
+    if (mfma) return hipErrorInvalidValue;
     prof_before(ctx, sizeof(R) == 8 ? "kq_c128" : "kq_c64", 2.0 * double(uint64_t(1) << n) * sizeof(V));
     hipLaunchKernelGGL((k_kq<R, K>), dim3(capped_grid((items + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                        ctx->stream, static_cast<V*>(s), items, ip, off, static_cast<const R*>(du));
@@ -645,13 +746,13 @@ hipError_t kq_launch(qsv_ctx ctx, void* s, int n, const int* pos, const void* du
 }
 
 template <typename R>
-hipError_t kq_t(qsv_ctx ctx, void* s, int n, int k, const int* pos, const void* du) {
+hipError_t kq_t(qsv_ctx ctx, void* s, int n, int k, const int* pos, const void* du, bool mfma) {
     switch (k) {
-    case 1: return kq_launch<R, 1>(ctx, s, n, pos, du);
-    case 2: return kq_launch<R, 2>(ctx, s, n, pos, du);
-    case 3: return kq_launch<R, 3>(ctx, s, n, pos, du);
-    case 4: return kq_launch<R, 4>(ctx, s, n, pos, du);
-    case 5: return kq_launch<R, 5>(ctx, s, n, pos, du);
+    case 1: return kq_launch<R, 1>(ctx, s, n, pos, du, mfma);
+    case 2: return kq_launch<R, 2>(ctx, s, n, pos, du, mfma);
+    case 3: return kq_launch<R, 3>(ctx, s, n, pos, du, mfma);
+    case 4: return kq_launch<R, 4>(ctx, s, n, pos, du, mfma);
+    case 5: return kq_launch<R, 5>(ctx, s, n, pos, du, mfma);
     default: return hipErrorInvalidValue;
     }
 }
@@ -673,8 +774,38 @@ hipError_t launch_apply2q(qsv_ctx ctx, void* s, int n, int dtype, int pa, int pb
     return dtype == QSV_C128 ? apply2q_t<double>(ctx, s, n, pa, pb, u)
                              : apply2q_t<float>(ctx, s, n, pa, pb, u);
 }
-hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du) {
-    return dtype == QSV_C128 ? kq_t<double>(ctx, s, n, k, pos, du) : kq_t<float>(ctx, s, n, k, pos, du);
+hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du, bool mfma) {
+    return dtype == QSV_C128 ? kq_t<double>(ctx, s, n, k, pos, du, mfma)
+                             : kq_t<float>(ctx, s, n, k, pos, du, mfma);
+}
+bool kq_mfma_applies(int n, int k, int mode) {
+    if (n - k < 6) return false;
+    // mode 1: where the matrix cores measured faster than the vector kernel
+    // (k = 3, 5; for k = 4 both run near the HBM rate and the vector kernel
+    // was slightly ahead); mode 2: every k in 3..5
+    return mode == 2 ? (k >= 3 && k <= 5) : mode == 1 ? (k == 3 || k == 5) : false;
+}
+void kq_mfma_pack(int dtype, int k, const double* u, void* out) {
+    const int D = 1 << k;
+    for (int rc = 0; rc < D / 8; ++rc)
+        for (int kc = 0; kc < D / 2; ++kc)
+            for (int lane = 0; lane < 64; ++lane) {
+                // A[i][kk] of the 16x16x4 MFMA sits on lane i + 16 kk; output
+                // row i of a slice is element i / 4 of lane group i mod 4 for
+                // the FP64 instruction and element i mod 4 of group i / 4 for
+                // the FP32 one
+                const int i = lane & 15, kk = lane >> 4;
+                const int g = dtype == QSV_C128 ? i % 4 : i / 4;
+                const int e = dtype == QSV_C128 ? i / 4 : i % 4;
+                const int co = 8 * rc + 2 * g + e / 2, po = e % 2;
+                const int ci = 4 * (kc / 2) + kk, pi = kc % 2;
+                const double re = u[2 * (co * D + ci)], im = u[2 * (co * D + ci) + 1];
+                // [[Re U, -Im U], [Im U, Re U]], rows and columns (re, im) per amplitude
+                const double v = po == 0 ? (pi == 0 ? re : -im) : (pi == 0 ? im : re);
+                const size_t at = size_t(rc * (D / 2) + kc) * 64 + size_t(lane);
+                if (dtype == QSV_C128) static_cast<double*>(out)[at] = v;
+                else static_cast<float*>(out)[at] = float(v);
+            }
 }
 hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g) {
     if (g.cm) return dtype == QSV_C128 ? mc_t<double>(ctx, s, n, g) : mc_t<float>(ctx, s, n, g);

@@ -259,6 +259,9 @@ struct qsv_ctx_s {
     // structure key -> chosen tile shape
     std::map<uint64_t, qsv::TileConfig> tuned_single;
 
+    // dense k-qubit gates on the matrix cores (qsv_set_matrix_cores)
+    int kq_mfma = 1;
+
     // host worker threads of the batch planner (started on first use)
     qsv::WorkerPool* pool = nullptr;
 
@@ -322,7 +325,13 @@ hipError_t launch_gate(qsv_ctx ctx, void* s, int n, int dtype, const PGate& g);
 // k-qubit gate (1 <= k <= 5) on index-bit positions pos[0..k) (pos[0] = most
 // significant local bit); du: the 2^k x 2^k matrix in device memory, in the
 // state's real type.
-hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du);
+hipError_t launch_kq(qsv_ctx ctx, void* s, int n, int dtype, int k, const int* pos, const void* du,
+                     bool mfma = false);
+// the matrix-core form of the k-qubit gate applies at this size and
+// qsv_set_matrix_cores mode; its matrix is 4^(k+1) reals in the lane order
+// kq_mfma_pack writes (u as for qsv_applyKq)
+bool kq_mfma_applies(int n, int k, int mode);
+void kq_mfma_pack(int dtype, int k, const double* u, void* out);
 
 // Largest tile (log2 amplitudes) the tile kernel supports for a dtype.
 int tile_bits_max(int dtype);

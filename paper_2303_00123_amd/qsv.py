@@ -48,7 +48,7 @@ EXPORTS = [
     "qsv_norm2", "qsv_expect_z", "qsv_inner", "qsv_prob1", "qsv_measure1", "qsv_copy_to_host",
     "qsv_copy_from_host", "qsv_adjoint", "qsv_batch_run", "qsv_profile_begin", "qsv_profile_end",
     "qsv_set_tile", "qsv_plan_circuit", "qsv_plan_fused", "qsv_applyMC1q", "qsv_applyKq",
-    "qsv_expect_z_dev", "qsv_set_jit", "qsv_jit_stats", "qsv_jit_source",
+    "qsv_expect_z_dev", "qsv_set_jit", "qsv_jit_stats", "qsv_jit_source", "qsv_set_matrix_cores",
 ]
 
 
@@ -93,6 +93,7 @@ def lib():
         "qsv_expect_z": [vp, i32, vp, vp, vp, vp],
         "qsv_expect_z_dev": [vp, i32, vp, vp],
         "qsv_set_jit": [vp, i32],
+        "qsv_set_matrix_cores": [vp, i32],
         "qsv_jit_stats": [vp, P(i32), P(d)],
         "qsv_jit_source": [i32, i32, vp, i64, vp, i64, i64, vp, sz, P(sz)],
         "qsv_inner": [vp, vp, vp],
@@ -199,6 +200,11 @@ class Context:
 
     def set_jit(self, mode: int):
         self.check(lib().qsv_set_jit(self.handle, mode))
+
+    def set_matrix_cores(self, mode: int):
+        """Dense k-qubit gates on the MFMA units: 1 (default) for k = 3 and 5,
+        2 for every k in 3..5, 0 never (vector units)."""
+        self.check(lib().qsv_set_matrix_cores(self.handle, mode))
 
     def jit_stats(self) -> tuple:
         k, t = ctypes.c_int(), ctypes.c_double()

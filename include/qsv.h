@@ -211,8 +211,10 @@ qsv_status qsv_applyKq(qsv_state st, int k, const int* qubits, const double* u);
  * shape -- (tile_bits, reg_bits, exchange) = (13, 5, split), (12, 4, split),
  * (12, 4, full), (12, 3, split), (11, 3, split) -- and keep the shape of the
  * fastest second run for later calls with the flag on this context; the
- * state ends as the circuit's result either way.  Calls without the flag
- * use the context's tile shape (qsv_set_tile). */
+ * state ends as the circuit's result either way.  With specialised kernels
+ * (qsv_set_jit) the tuning call also compiles every candidate shape's pass
+ * kernels.  Calls without the flag use the context's tile shape
+ * (qsv_set_tile). */
 qsv_status qsv_apply_circuit(qsv_state st, const qsv_gate* g, int64_t ng, const double* params,
                              int64_t nparams, int flags);
 

@@ -285,7 +285,10 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
 
 /* ----------------------------------------------------------------- batch */
 
-/* Run nb independent circuits in one persistent launch.  Circuit b has
+/* Run nb independent circuits in one persistent launch (for nb >= 32 two
+ * launches, one after the other on the same stream, each over half the
+ * circuits: the second half is planned and staged on the host while the
+ * first one runs).  Circuit b has
  * nq[b] qubits (1 <= nq[b] <= 24), gates g[gate_off[b] .. gate_off[b+1]),
  * rotation angles from params (indices global to the batch), starts in
  * |0..0> and yields out[b] = sum over terms t in [term_off[b], term_off[b+1])
@@ -297,11 +300,13 @@ qsv_status qsv_adjoint(qsv_state psi, qsv_state lam, const qsv_gate* g, int64_t 
  * of one tile never leave the workgroup.
  * QSV_FLAG_TUNE: on the first call for a batch shape (qubit counts, gate
  * kinds and qubits, observable terms -- not the angles) time each candidate
- * tile shape once and keep the fastest for later calls (file cache if the
- * environment variable QSV_TUNE_CACHE names one).
+ * tile shape (best of two runs of the whole batch in one launch) and keep
+ * the fastest for later calls (file cache if the environment variable
+ * QSV_TUNE_CACHE names one).
  * QSV_FLAG_CAPTURE_GRAPH: capture upload, counter reset, kernel and result
- * download in a hipGraph on a library-owned stream, and replay it on later
- * calls with the same batch shape (new angles are uploaded by the replay).
+ * download in a hipGraph (one per launch) on a library-owned stream, and
+ * replay it on later calls with the same batch shape (new angles are
+ * uploaded by the replay).
  * Synchronises before returning.
  * Errors: a workgroup that waits for the previous pass of its circuit gives
  * up after a bounded number of sleeps (about 2 s; the environment variable

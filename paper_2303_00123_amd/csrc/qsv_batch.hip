@@ -62,6 +62,8 @@ struct BItem {
 
 // counters layout (uint32): [0] next item, [1] error flag, [2 ..) done per circuit
 constexpr int kCtrDone = 2;
+// batches of at least this many circuits run as two parts (see qsv_batch_run)
+constexpr int kSplitCircuits = 32;
 
 __device__ __forceinline__ double zsign_sum(uint64_t x, const uint64_t* __restrict__ m,
                                             const double* __restrict__ w, int beg, int end) {
@@ -536,17 +538,17 @@ struct BatchRun {
     int nitems = 0;
 };
 
-// Enqueue one batch (upload, counter reset, kernel, result download) on
-// `stream`, using the context's batch buffers (grown on demand beforehand).
-static hipError_t enqueue_batch(qsv_ctx ctx, hipStream_t stream, int dtype, int K, int nb,
+// Enqueue one part of a batch (upload, counter reset, kernel, result
+// download) on `stream`, with slot b's buffers (grown on demand beforehand).
+static hipError_t enqueue_batch(qsv_ctx ctx, BatchSlot& b, hipStream_t stream, int dtype, int K, int nb,
                                 const BatchRun& R) {
-    char* dev = static_cast<char*>(ctx->d_batch);
-    hipError_t e = hipMemcpyAsync(dev, ctx->h_batch, R.L.total, hipMemcpyHostToDevice, stream);
+    char* dev = static_cast<char*>(b.d);
+    hipError_t e = hipMemcpyAsync(dev, b.h, R.L.total, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return e;
-    unsigned* ctr = reinterpret_cast<unsigned*>(dev + ctx->batch_ctr_off);
-    double* out = reinterpret_cast<double*>(dev + ctx->batch_out_off);
-    double* partials = reinterpret_cast<double*>(dev + ctx->batch_part_off);
-    void* states = dev + ctx->batch_state_off;
+    unsigned* ctr = reinterpret_cast<unsigned*>(dev + b.ctr_off);
+    double* out = reinterpret_cast<double*>(dev + b.out_off);
+    double* partials = reinterpret_cast<double*>(dev + b.part_off);
+    void* states = dev + b.state_off;
     const size_t zw = R.ctr_words;   // item counter, error flag, per-circuit completion counts
     hipLaunchKernelGGL(k_zero, dim3(unsigned((zw + 255) / 256)), dim3(256), 0, stream, ctr, zw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -556,19 +558,19 @@ static hipError_t enqueue_batch(qsv_ctx ctx, hipStream_t stream, int dtype, int 
             : launch_batch_k<float>(ctx, stream, K, dev, R.L, nb, R.nitems, states, ctr, partials, out);
     prof_after_on(ctx, stream);
     if (e != hipSuccess) return e;
-    return hipMemcpyAsync(ctx->h_batch_out, out, sizeof(double) * (size_t(nb) + 1),
-                          hipMemcpyDeviceToHost, stream);
+    return hipMemcpyAsync(b.h_out, out, sizeof(double) * (size_t(nb) + 1), hipMemcpyDeviceToHost, stream);
 }
 
-// Plan and stage a batch for tile shape (K, L); sizes the context buffers.
-static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t* gate_off,
+// Plan and stage nb circuits into slot b for tile shape (K, L); sizes the
+// slot's buffers.
+static qsv_status stage_batch(qsv_ctx ctx, BatchSlot& b, int nb, const int* nq, const int64_t* gate_off,
                               const qsv_gate* g, const double* params, int64_t nparams,
                               const int64_t* term_off, const uint64_t* qmasks, const double* w,
                               int dtype, int K, int L, BatchRun& R, uint64_t& key) {
     BatchBuild B;
     const auto t0 = std::chrono::steady_clock::now();
     std::string err = build_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
-                                  K, L, B, &ctx->batch_memo);
+                                  K, L, B, &b.memo);
     const auto t1 = std::chrono::steady_clock::now();
     if (!err.empty()) {
         ctx->last_error = "qsv_batch_run: " + err;
@@ -586,59 +588,58 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     const size_t part_off = align256(out_off + (size_t(nb) + 1) * sizeof(double));
     const size_t state_off = align256(part_off + (R.partial_count + 1) * sizeof(double));
     const size_t need = state_off + R.state_bytes + 256;
-    if (need > ctx->batch_bytes || R.L.total > ctx->h_batch_bytes ||
-        size_t(nb) + 1 > ctx->h_batch_out_n) {
+    if (need > b.d_bytes || R.L.total > b.h_bytes || size_t(nb) + 1 > b.h_out_n) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess && ctx->batch_stream) e = hipStreamSynchronize(ctx->batch_stream);
         if (e != hipSuccess) {
             ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
             return QSV_ERR_HIP;
         }
-        if (ctx->batch_graph_exec) {
-            hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
-            ctx->batch_graph_exec = nullptr;
-            ctx->batch_graph_key = 0;
+        if (b.graph_exec) {
+            hipGraphExecDestroy(static_cast<hipGraphExec_t>(b.graph_exec));
+            b.graph_exec = nullptr;
+            b.graph_key = 0;
         }
-        if (need > ctx->batch_bytes) {
-            if (ctx->d_batch) hipFree(ctx->d_batch);
-            ctx->d_batch = nullptr;
-            ctx->batch_bytes = 0;
-            if (hipMalloc(&ctx->d_batch, need) != hipSuccess) {
+        if (need > b.d_bytes) {
+            if (b.d) hipFree(b.d);
+            b.d = nullptr;
+            b.d_bytes = 0;
+            if (hipMalloc(&b.d, need) != hipSuccess) {
                 (void)hipGetLastError();
                 ctx->last_error = "qsv_batch_run: device allocation of " + std::to_string(need) + " bytes failed";
                 return QSV_ERR_NOMEM;
             }
-            ctx->batch_bytes = need;
+            b.d_bytes = need;
         }
-        if (R.L.total > ctx->h_batch_bytes) {
-            if (ctx->h_batch) hipHostFree(ctx->h_batch);
-            ctx->h_batch = nullptr;
-            ctx->h_batch_bytes = 0;
-            if (hipHostMalloc(&ctx->h_batch, R.L.total, hipHostMallocDefault) != hipSuccess) {
+        if (R.L.total > b.h_bytes) {
+            if (b.h) hipHostFree(b.h);
+            b.h = nullptr;
+            b.h_bytes = 0;
+            if (hipHostMalloc(&b.h, R.L.total, hipHostMallocDefault) != hipSuccess) {
                 (void)hipGetLastError();
                 ctx->last_error = "qsv_batch_run: pinned allocation failed";
                 return QSV_ERR_NOMEM;
             }
-            ctx->h_batch_bytes = R.L.total;
+            b.h_bytes = R.L.total;
         }
-        if (size_t(nb) + 1 > ctx->h_batch_out_n) {
-            if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
-            ctx->h_batch_out = nullptr;
-            ctx->h_batch_out_n = 0;
-            if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_batch_out), sizeof(double) * (size_t(nb) + 1),
+        if (size_t(nb) + 1 > b.h_out_n) {
+            if (b.h_out) hipHostFree(b.h_out);
+            b.h_out = nullptr;
+            b.h_out_n = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&b.h_out), sizeof(double) * (size_t(nb) + 1),
                               hipHostMallocDefault) != hipSuccess) {
                 (void)hipGetLastError();
                 ctx->last_error = "qsv_batch_run: pinned allocation failed";
                 return QSV_ERR_NOMEM;
             }
-            ctx->h_batch_out_n = size_t(nb) + 1;
+            b.h_out_n = size_t(nb) + 1;
         }
     }
-    ctx->batch_ctr_off = ctr_off;
-    ctx->batch_out_off = out_off;
-    ctx->batch_part_off = part_off;
-    ctx->batch_state_off = state_off;
-    char* h = static_cast<char*>(ctx->h_batch);
+    b.ctr_off = ctr_off;
+    b.out_off = out_off;
+    b.part_off = part_off;
+    b.state_off = state_off;
+    char* h = static_cast<char*>(b.h);
     if (qsv_status ws = write_batch_records(ctx, B, h + R.L.plan)) {
         ctx->last_error = ws == QSV_ERR_NOMEM ? "qsv_batch_run: out of host memory while writing records"
                                               : "qsv_batch_run: internal planner error";
@@ -651,28 +652,81 @@ static qsv_status stage_batch(qsv_ctx ctx, int nb, const int* nq, const int64_t*
     if (!B.tw.empty()) std::memcpy(h + R.L.tw, B.tw.data(), B.tw.size() * sizeof(double));
     if (log_enabled()) {
         const auto t2 = std::chrono::steady_clock::now();
-        logf("batch staging: build %.2f ms, records and copies %.2f ms",
-             std::chrono::duration<double, std::milli>(t1 - t0).count(),
+        logf("batch staging: %d circuits, %d items, tile 2^%d low %d, build %.2f ms, records and copies %.2f ms",
+             nb, R.nitems, K, L, std::chrono::duration<double, std::milli>(t1 - t0).count(),
              std::chrono::duration<double, std::milli>(t2 - t1).count());
     }
     return QSV_OK;
 }
 
-static qsv_status finish_batch(qsv_ctx ctx, hipStream_t stream, int nb, double* out) {
-    hipError_t e = hipStreamSynchronize(stream);
+// Wait for `stream`; check a part's error flag.
+static qsv_status wait_batch(qsv_ctx ctx, hipStream_t stream) {
+    const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorName(e) + " " + hipGetErrorString(e);
         return QSV_ERR_HIP;
     }
+    return QSV_OK;
+}
+static qsv_status check_batch(qsv_ctx ctx, const BatchSlot& b) {
     unsigned flag = 0;
-    e = hipMemcpy(&flag, static_cast<char*>(ctx->d_batch) + ctx->batch_ctr_off + sizeof(unsigned),
-                  sizeof(unsigned), hipMemcpyDeviceToHost);
+    const hipError_t e = hipMemcpy(&flag, static_cast<const char*>(b.d) + b.ctr_off + sizeof(unsigned),
+                                   sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess || flag) {
         ctx->last_error = "qsv_batch_run: a dependency wait exceeded its spin limit";
         return QSV_ERR_HIP;
     }
-    std::memcpy(out, ctx->h_batch_out, sizeof(double) * size_t(nb));
     return QSV_OK;
+}
+
+// Launch a staged part on `stream`: its captured graph (captured anew when
+// anything it bakes in changed) or the eager sequence.
+static hipError_t launch_part(qsv_ctx ctx, BatchSlot& b, hipStream_t stream, bool graph, int dtype, int K,
+                              int L, int nb, const BatchRun& R, uint64_t key) {
+    if (!graph) return enqueue_batch(ctx, b, stream, dtype, K, nb, R);
+    // everything the captured graph bakes in: tile shape, upload layout,
+    // item count (grid), counter words, buffer offsets and sizes -- new
+    // angles can change fused gates and pass counts, so the shape key
+    // alone does not fix them
+    uint64_t gkey = key;
+    for (uint64_t v : {uint64_t(K), uint64_t(L), uint64_t(R.L.plan), uint64_t(R.L.circs),
+                       uint64_t(R.L.passes), uint64_t(R.L.items), uint64_t(R.L.tmask),
+                       uint64_t(R.L.tw), uint64_t(R.L.total), uint64_t(R.nitems),
+                       uint64_t(R.ctr_words), uint64_t(R.partial_count), uint64_t(R.state_bytes),
+                       uint64_t(b.ctr_off), uint64_t(b.out_off), uint64_t(b.part_off), uint64_t(b.state_off),
+                       reinterpret_cast<uint64_t>(b.d), reinterpret_cast<uint64_t>(b.h),
+                       reinterpret_cast<uint64_t>(b.h_out)})
+        mix(gkey, v);
+    hipError_t e = hipSuccess;
+    if (!b.graph_exec || b.graph_key != gkey) {
+        // capture from an idle stream (an earlier part may still run on it)
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        if (b.graph_exec) {
+            hipGraphExecDestroy(static_cast<hipGraphExec_t>(b.graph_exec));
+            b.graph_exec = nullptr;
+        }
+        hipGraph_t gr = nullptr;
+        e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const bool prof = ctx->profiling;
+            ctx->profiling = false;   // no event records inside the graph
+            const hipError_t e2 = enqueue_batch(ctx, b, stream, dtype, K, nb, R);
+            ctx->profiling = prof;
+            e = hipStreamEndCapture(stream, &gr);
+            if (e2 != hipSuccess) e = e2;
+        }
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        if (gr) hipGraphDestroy(gr);
+        if (e != hipSuccess) return e;
+        b.graph_exec = exec;
+        b.graph_key = gkey;
+    }
+    prof_before_on(ctx, stream, dtype == QSV_C128 ? "batch_graph_c128" : "batch_graph_c64", 0.0);
+    e = hipGraphLaunch(static_cast<hipGraphExec_t>(b.graph_exec), stream);
+    prof_after_on(ctx, stream);
+    return e;
 }
 
 // Key of a batch's shape: qubit counts, gate kinds / qubits / control states /
@@ -750,7 +804,6 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
             return QSV_ERR_ARG;
         }
         // tile shape: the tuned choice for this batch shape, if any
-        BatchRun R;
         uint64_t key = 0;
         int K = dtype == QSV_C128 ? 12 : 13, L = dtype == QSV_C128 ? 3 : 4;
         {
@@ -768,8 +821,8 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                     if (sh[0] >= 13 && dtype == QSV_C128) continue;   // not compiled (see launch_batch_k)
                     uint64_t k2 = 0;
                     BatchRun Rc;
-                    s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w, dtype,
-                                    sh[0], sh[1], Rc, k2);
+                    s = stage_batch(ctx, ctx->batch[0], nb, nq, gate_off, g, params, nparams, term_off, qmasks,
+                                    w, dtype, sh[0], sh[1], Rc, k2);
                     if (s != QSV_OK) return s;
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -782,9 +835,12 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                     hipError_t e = hipSuccess;
                     for (int rep = 0; rep < 2 && e == hipSuccess && s == QSV_OK; ++rep) {
                         hipEventRecord(e0, ctx->stream);
-                        e = enqueue_batch(ctx, ctx->stream, dtype, sh[0], nb, Rc);
+                        e = enqueue_batch(ctx, ctx->batch[0], ctx->stream, dtype, sh[0], nb, Rc);
                         hipEventRecord(e1, ctx->stream);
-                        if (e == hipSuccess) s = finish_batch(ctx, ctx->stream, nb, out);
+                        if (e == hipSuccess) s = wait_batch(ctx, ctx->stream);
+                        if (e == hipSuccess && s == QSV_OK) s = check_batch(ctx, ctx->batch[0]);
+                        if (e == hipSuccess && s == QSV_OK)
+                            std::memcpy(out, ctx->batch[0].h_out, sizeof(double) * size_t(nb));
                         float t = 0.f;
                         if (e == hipSuccess && s == QSV_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
                             t < ms)
@@ -806,86 +862,56 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx ctx, int nb, const int* nq, const in
                 tune_store(ctx, key, dtype, K, L, best);
             }
         }
-        const auto t0 = std::chrono::steady_clock::now();
-        qsv_status s = stage_batch(ctx, nb, nq, gate_off, g, params, nparams, term_off, qmasks, w,
-                                   dtype, K, L, R, key);
-        if (s != QSV_OK) return s;
-        if (log_enabled()) {
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            logf("batch: %d circuits, %d items, tile 2^%d low %d, plan %zu B, states %zu B, host planning %.2f ms",
-                 nb, R.nitems, K, L, R.L.total, R.state_bytes, ms);
-        }
-        hipError_t e;
-        if (flags & QSV_FLAG_CAPTURE_GRAPH) {
+        // Two parts when the batch is large enough: the second part is staged
+        // on the host while the first one runs on the GPU.  Each part has its
+        // own buffers, plan memo and captured graph; both run on one stream.
+        const bool graph = (flags & QSV_FLAG_CAPTURE_GRAPH) != 0;
+        hipStream_t stream = ctx->stream;
+        if (graph) {
             if (!ctx->batch_stream) {
                 if (hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking) != hipSuccess) {
                     ctx->last_error = "qsv_batch_run: stream creation failed";
                     return QSV_ERR_HIP;
                 }
             }
-            // everything the captured graph bakes in: tile shape, upload layout,
-            // item count (grid), counter words, buffer offsets and sizes -- new
-            // angles can change fused gates and pass counts, so the shape key
-            // alone does not fix them
-            uint64_t gkey = key;
-            for (uint64_t v : {uint64_t(K), uint64_t(L), uint64_t(R.L.plan), uint64_t(R.L.circs),
-                               uint64_t(R.L.passes), uint64_t(R.L.items), uint64_t(R.L.tmask),
-                               uint64_t(R.L.tw), uint64_t(R.L.total), uint64_t(R.nitems),
-                               uint64_t(R.ctr_words), uint64_t(R.partial_count), uint64_t(R.state_bytes),
-                               uint64_t(ctx->batch_ctr_off), uint64_t(ctx->batch_out_off),
-                               uint64_t(ctx->batch_part_off), uint64_t(ctx->batch_state_off),
-                               reinterpret_cast<uint64_t>(ctx->d_batch)})
-                mix(gkey, v);
+            stream = ctx->batch_stream;
             // order the batch after the context stream's earlier work
-            e = hipStreamSynchronize(ctx->stream);
-            if (e == hipSuccess && (!ctx->batch_graph_exec || ctx->batch_graph_key != gkey)) {
-                if (ctx->batch_graph_exec) {
-                    hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
-                    ctx->batch_graph_exec = nullptr;
-                }
-                hipGraph_t graph = nullptr;
-                e = hipStreamBeginCapture(ctx->batch_stream, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) {
-                    const bool prof = ctx->profiling;
-                    ctx->profiling = false;   // no event records inside the graph
-                    hipError_t e2 = enqueue_batch(ctx, ctx->batch_stream, dtype, K, nb, R);
-                    ctx->profiling = prof;
-                    e = hipStreamEndCapture(ctx->batch_stream, &graph);
-                    if (e2 != hipSuccess) e = e2;
-                }
-                hipGraphExec_t exec = nullptr;
-                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                if (graph) hipGraphDestroy(graph);
-                if (e == hipSuccess) {
-                    ctx->batch_graph_exec = exec;
-                    ctx->batch_graph_key = gkey;
-                }
-            }
-            if (e == hipSuccess) {
-                prof_before_on(ctx, ctx->batch_stream, dtype == QSV_C128 ? "batch_graph_c128" : "batch_graph_c64", 0.0);
-                e = hipGraphLaunch(static_cast<hipGraphExec_t>(ctx->batch_graph_exec), ctx->batch_stream);
-                prof_after_on(ctx, ctx->batch_stream);
-            }
+            const hipError_t e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) {
-                ctx->last_error = std::string("qsv_batch_run (graph): ") + hipGetErrorString(e);
+                ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
                 return QSV_ERR_HIP;
             }
-            const auto t_launched = std::chrono::steady_clock::now();
-            const qsv_status fs = finish_batch(ctx, ctx->batch_stream, nb, out);
-            if (log_enabled()) {
-                const auto t_done = std::chrono::steady_clock::now();
-                logf("batch call: %.2f ms to launch, %.2f ms waiting and reading results",
-                     std::chrono::duration<double, std::milli>(t_launched - t_entry).count(),
-                     std::chrono::duration<double, std::milli>(t_done - t_launched).count());
+        }
+        // (three or four parts measured no faster: each launch adds a drain tail)
+        const int parts = nb >= kSplitCircuits ? 2 : 1;
+        const int first[3] = {0, parts == 2 ? nb / 2 : nb, nb};
+        for (int p = 0; p < parts; ++p) {
+            const int c0 = first[p], np = first[p + 1] - first[p];
+            BatchRun R;
+            uint64_t pkey = 0;
+            qsv_status s = stage_batch(ctx, ctx->batch[p], np, nq + c0, gate_off + c0, g, params, nparams,
+                                       term_off + c0, qmasks, w, dtype, K, L, R, pkey);
+            if (s != QSV_OK) return s;
+            const hipError_t e = launch_part(ctx, ctx->batch[p], stream, graph, dtype, K, L, np, R, pkey);
+            if (e != hipSuccess) {
+                ctx->last_error = std::string(graph ? "qsv_batch_run (graph): " : "qsv_batch_run: ") +
+                                  hipGetErrorString(e);
+                return QSV_ERR_HIP;
             }
-            return fs;
         }
-        e = enqueue_batch(ctx, ctx->stream, dtype, K, nb, R);
-        if (e != hipSuccess) {
-            ctx->last_error = std::string("qsv_batch_run: ") + hipGetErrorString(e);
-            return QSV_ERR_HIP;
+        const auto t_launched = std::chrono::steady_clock::now();
+        if (qsv_status s = wait_batch(ctx, stream)) return s;
+        for (int p = 0; p < parts; ++p)   // every part checked before out is written
+            if (qsv_status s = check_batch(ctx, ctx->batch[p])) return s;
+        for (int p = 0; p < parts; ++p)
+            std::memcpy(out + first[p], ctx->batch[p].h_out, sizeof(double) * size_t(first[p + 1] - first[p]));
+        if (log_enabled()) {
+            const auto t_done = std::chrono::steady_clock::now();
+            logf("batch call: %d part(s), %.2f ms to launch, %.2f ms waiting and reading results", parts,
+                 std::chrono::duration<double, std::milli>(t_launched - t_entry).count(),
+                 std::chrono::duration<double, std::milli>(t_done - t_launched).count());
         }
-        return finish_batch(ctx, ctx->stream, nb, out);
+        return QSV_OK;
     } catch (const std::bad_alloc&) {
         return QSV_ERR_NOMEM;
     } catch (...) {

@@ -318,10 +318,12 @@ qsv_status qsv_ctx_destroy(qsv_ctx ctx) {
         if (ctx->plan_copied) hipEventDestroy(ctx->plan_copied);
         for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
         if (ctx->batch_stream) hipStreamSynchronize(ctx->batch_stream);
-        if (ctx->batch_graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(ctx->batch_graph_exec));
-        if (ctx->d_batch) hipFree(ctx->d_batch);
-        if (ctx->h_batch) hipHostFree(ctx->h_batch);
-        if (ctx->h_batch_out) hipHostFree(ctx->h_batch_out);
+        for (qsv::BatchSlot& b : ctx->batch) {
+            if (b.graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(b.graph_exec));
+            if (b.d) hipFree(b.d);
+            if (b.h) hipHostFree(b.h);
+            if (b.h_out) hipHostFree(b.h_out);
+        }
         if (ctx->batch_stream) hipStreamDestroy(ctx->batch_stream);
         jit_release(ctx);
         pool_destroy(ctx->pool);

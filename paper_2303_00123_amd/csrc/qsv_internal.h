@@ -183,6 +183,22 @@ struct PlanMemo {
 }  // namespace qsv
 
 namespace qsv {
+// Buffers of one part of a batch call: device [upload | counters | out |
+// partials | states], pinned staging and results, the captured graph and
+// the per-circuit plan memo.
+struct BatchSlot {
+    void* d = nullptr;
+    size_t d_bytes = 0;
+    void* h = nullptr;
+    size_t h_bytes = 0;
+    double* h_out = nullptr;
+    size_t h_out_n = 0;
+    size_t ctr_off = 0, out_off = 0, part_off = 0, state_off = 0;
+    void* graph_exec = nullptr;   // hipGraphExec_t
+    uint64_t graph_key = 0;
+    std::vector<PlanMemo> memo;
+};
+
 // Host worker threads that run f(arg, i) for i in [0, n) together with the
 // calling thread (qsv_pool.cpp).  pool_run returns false if a call threw;
 // one caller at a time per pool.
@@ -227,17 +243,10 @@ struct qsv_ctx_s {
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
 
-    // batch: device buffer [upload | counters | out | partials | states], pinned staging
-    void* d_batch = nullptr;
-    size_t batch_bytes = 0;
-    void* h_batch = nullptr;
-    size_t h_batch_bytes = 0;
-    double* h_batch_out = nullptr;
-    size_t h_batch_out_n = 0;
-    size_t batch_ctr_off = 0, batch_out_off = 0, batch_part_off = 0, batch_state_off = 0;
+    // batch: a call runs in up to two parts (qsv_batch.hip), each with its
+    // own buffers, plan memo and captured graph
+    qsv::BatchSlot batch[2];
     hipStream_t batch_stream = nullptr;   // capture stream (default priority)
-    void* batch_graph_exec = nullptr;     // hipGraphExec_t
-    uint64_t batch_graph_key = 0;
 
     // autotuner choices: batch shape key -> (tile_bits, low_bits)
     std::map<uint64_t, std::pair<int, int>> tuned;
@@ -252,7 +261,6 @@ struct qsv_ctx_s {
     std::vector<qsv::PGate> cache_pg;   // fused gates
     qsv::PlanMemo memo;                 // their passes
     bool plan_resident = false;         // d_plan holds the records of memo.passes
-    std::vector<qsv::PlanMemo> batch_memo;   // per circuit of the last batch
     qsv::PlanMemo adj_memo;             // passes of the last adjoint sweep's reversed circuit
 
     // single-state tuner (QSV_FLAG_TUNE on qsv_apply_circuit): circuit

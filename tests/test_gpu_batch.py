@@ -78,6 +78,26 @@ def test_batch_graph_replays_with_new_angles(q, ctx):
         assert np.max(np.abs(eager - got)) <= 1e-12
 
 
+def test_two_part_batch_graph_and_eager(q, ctx):
+    """37 circuits (an odd count above the split size: two launches of 18
+    and 19): graph replays with new angles and the eager path against the
+    oracle, in both precisions."""
+    circs = (mixed_batch(4) * 4)[:37]
+    circs = [W.Circuit(c.n, list(c.gates), np.array(c.params, dtype=float), list(c.observable)) for c in circs]
+    rng = np.random.default_rng(11)
+    for rep in range(3):
+        for c in circs:
+            if c.params.size:
+                c.params = rng.uniform(0, 2 * np.pi, size=c.params.size)
+        ref = oracle_values(circs)
+        for dtype in (2, 1):
+            got = ctx.batch_run(circs, dtype, flags=q.FLAG_CAPTURE_GRAPH)
+            eager = ctx.batch_run(circs, dtype)
+            for b, c in enumerate(circs):
+                assert abs(got[b] - ref[b]) <= tol(c, dtype), (rep, dtype, b)
+                assert abs(eager[b] - ref[b]) <= tol(c, dtype), (rep, dtype, b)
+
+
 def test_batch_tuned_shape_is_correct_and_cached(q, ctx):
     circs = mixed_batch(3)
     ref = oracle_values(circs)

@@ -174,3 +174,49 @@ def test_unfused_grid_stride_loops_sampled(dt_name, n, tol_amp):
         ctx.close()
         del st
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt_name,n,tol_amp", [("c128", 32, 1e-12), ("c64", 33, 1e-6)])
+def test_matrix_core_kq_grid_stride_sampled(dt_name, n, tol_amp):
+    """A dense 3-qubit gate on the matrix cores at 32 (c128) / 33 (c64)
+    qubits, 64 GiB: 2^(n-3)/64 blocks exceed the capped grid, so the kernel
+    walks several blocks per workgroup in XCD order.  A Haar gate on every
+    qubit first (a product state), then U on qubits (n-1, 0, n//2) (lowest,
+    highest and a middle index bit).  Each sampled amplitude is the oracle's
+    product over the other qubits times the oracle's 3-qubit subsystem
+    amplitude."""
+    import torch
+    import paper_2303_00123_amd as q
+    dt = q.QSV_C128 if dt_name == "c128" else q.QSV_C64
+    _device_or_skip((2 ** n) * (16 if dt == q.QSV_C128 else 8))
+    rng = np.random.default_rng(3500 + n)
+    us = [W.haar_unitary(2, rng) for _ in range(n)]
+    u = W.haar_unitary(8, rng)
+    qs = [n - 1, 0, n // 2]
+    qstates = np.array([O.apply_1q(O.basis(1), 0, v) for v in us])
+    sub = O.apply_kq(np.kron(np.kron(qstates[qs[0]], qstates[qs[1]]), qstates[qs[2]]), [0, 1, 2], u)
+    ones = np.array([1.0 + 0j, 1.0 + 0j])
+    rest = qstates.copy()
+    for qb in qs:
+        rest[qb] = ones
+    ctx = q.Context()
+    ctx.set_matrix_cores(1)
+    st = q.State(ctx, n, dt)
+    try:
+        st.init_basis(0)
+        st.apply_circuit([W.g1(qb, us[qb]) for qb in range(n)])
+        ctx.profile_begin()
+        st.applyKq(qs, u)
+        assert list(ctx.profile_end()) == [f"kq_mfma_{dt_name}"]
+        xs = np.concatenate([[0, 2 ** n - 1, 1, 2 ** (n - 1), 2 ** (n // 2)],
+                             rng.integers(0, 2 ** n, size=60)]).astype(np.int64)
+        got = st.tensor[torch.as_tensor(xs, device="cuda")].cpu().numpy().astype(np.complex128)
+        bit = lambda x, qb: (x >> (n - 1 - qb)) & 1   # noqa: E731
+        ref = np.array([O.product_amplitude(rest, int(x))
+                        * sub[4 * bit(x, qs[0]) + 2 * bit(x, qs[1]) + bit(x, qs[2])] for x in map(int, xs)])
+        assert np.max(np.abs(got - ref)) < tol_amp
+    finally:
+        st.free()
+        ctx.close()
+        del st
+        torch.cuda.empty_cache()

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
 the same seeded inputs.  complex128 amplitudes must agree to 1e-12 (max abs);
-complex64 results are judged by infidelity 1 - |<psi64|psi128>|^2 <= 1e-6."""
+complex64 results are checked by infidelity 1 - |<psi64|psi128>|^2 <= 1e-6."""
 import numpy as np
 import pytest
 

@@ -448,7 +448,7 @@ def batch_bench(q, W, dtype, reps: int = 5):
     the GPU time of the replayed hipGraphs."""
     import torch
     import numpy as np
-    circs = W.config4()
+    circs = W.ladder_batch_256()
     spec = q.BatchSpec(circs)
     ctx = q.Context()
     ctx.batch_run(spec, dtype, flags=q.FLAG_TUNE)

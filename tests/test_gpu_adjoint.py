@@ -59,11 +59,11 @@ def test_fused_adjoint_vs_unfused_and_oracle(q, ctx, maker):
     assert np.max(np.abs(g3 - g_ref)) <= 1e-4 * wsum(c)
 
 
-def test_config5_adjoint_vs_gpu_parameter_shift(q, ctx):
+def test_hea24_adjoint_vs_gpu_parameter_shift(q, ctx):
     """24 qubits, 10 layers RY,RZ + CZ ring, 480 parameters: the fused adjoint
     gradient against parameter shift on 24 sampled parameters, each shifted
     energy evaluated with the (oracle-validated) GPU forward pass."""
-    c = W.config5()
+    c = W.hea_n24()
     psi, lam = q.State(ctx, c.n), q.State(ctx, c.n)
     f, g = q.adjoint(psi, lam, c.gates, c.params, c.observable)
     g_unf = q.adjoint(psi, lam, c.gates, c.params, c.observable,
@@ -130,7 +130,7 @@ def test_adjoint_through_general_fixed_gates(q, ctx, n, layers, seed):
 
 
 @pytest.mark.parametrize("dt_name", ["c128", "c64"])
-def test_config5_ansatz_20_qubits_vs_oracle_adjoint(q, ctx, dt_name):
+def test_hea_ansatz_20_qubits_vs_oracle_adjoint(q, ctx, dt_name):
     """The configuration's ansatz (10 layers of RY, RZ on every qubit + CZ
     ring, open-chain ZZ observable with N(0,1) weights) at 20 qubits, 400
     parameters: every gradient component of the fused sweep against one

@@ -108,10 +108,10 @@ def test_batch_tuned_shape_is_correct_and_cached(q, ctx):
 
 
 @pytest.mark.parametrize("dtype", [2, 1])
-def test_config4_batch_vs_single_state_path(q, ctx, dtype):
+def test_ladder_batch_vs_single_state_path(q, ctx, dtype):
     """256 circuits, 12..20 qubits, 6 layers RY RZ + CNOT ladder: each batch
     result against the same circuit run alone through qsv_apply_circuit."""
-    circs = W.config4()
+    circs = W.ladder_batch_256()
     got = ctx.batch_run(circs, dtype)
     for b, c in enumerate(circs):
         st = q.State(ctx, c.n, dtype)
@@ -123,30 +123,30 @@ def test_config4_batch_vs_single_state_path(q, ctx, dtype):
 
 
 @pytest.fixture(scope="module")
-def config4_oracle():
-    """<sum_i Z_i> of every config-4 circuit (256 circuits, 12..20 qubits)
+def ladder_batch_oracle():
+    """<sum_i Z_i> of every circuit of the 256-circuit ladder batch (256 circuits, 12..20 qubits)
     from the FP64 oracle: about a minute on the host, shared by both dtypes."""
-    circs = W.config4()
+    circs = W.ladder_batch_256()
     vals = []
     for b, c in enumerate(circs):
         vals.append(O.expect_obs(O.run(c), c.observable))
         if b % 64 == 63:
-            print(f"config-4 oracle: {b + 1}/{len(circs)} circuits", flush=True)
+            print(f"ladder batch oracle: {b + 1}/{len(circs)} circuits", flush=True)
     return circs, np.array(vals)
 
 
 @pytest.mark.parametrize("dtype", [2, 1])
-def test_config4_every_circuit_vs_oracle(q, ctx, config4_oracle, dtype):
-    """All 256 config-4 circuits (12..20 qubits, every width present) in one
+def test_ladder_batch_every_circuit_vs_oracle(q, ctx, ladder_batch_oracle, dtype):
+    """All 256 ladder-batch circuits (12..20 qubits, every width present) in one
     batch launch against the FP64 oracle's final state and observable:
     complex128 to 1e-11, complex64 to 1e-5 per qubit of the observable."""
-    circs, ref = config4_oracle
+    circs, ref = ladder_batch_oracle
     assert {c.n for c in circs} == set(range(12, 21))
     got = ctx.batch_run(circs, dtype)
     for b, c in enumerate(circs):
         assert abs(got[b] - ref[b]) <= (1e-11 if dtype == 2 else 1e-5 * c.n), (b, c.n, got[b], ref[b])
     err = np.max(np.abs(got - ref))
-    print(f"config-4 batch, dtype {dtype}: max |d <sum Z>| = {err:.3e}", flush=True)
+    print(f"ladder batch, dtype {dtype}: max |d <sum Z>| = {err:.3e}", flush=True)
 
 
 def test_batch_rejects_bad_input(q, ctx):

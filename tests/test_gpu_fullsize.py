@@ -98,12 +98,12 @@ def test_c64_matches_c128_full_size(q, ctx):
     a.free()
 
 
-def test_config2_28_qubits_fused_vs_one_kernel_per_gate(q, ctx):
+def test_brick28_fused_vs_one_kernel_per_gate(q, ctx):
     """28-qubit brick circuit (20 layers): the fused tile passes the benchmark
     times against one kernel per gate (Algs. 1-3, separately checked against
     the oracle), amplitude by amplitude on the GPU; norm and <Z0 Z27>."""
     import torch
-    c = W.config2()
+    c = W.brick_n28()
     a = q.State(ctx, c.n)
     a.init_basis(0)
     a.apply_circuit(c.gates)
@@ -119,7 +119,7 @@ def test_config2_28_qubits_fused_vs_one_kernel_per_gate(q, ctx):
     b.free()
 
 
-def test_config3_32_qubits_c64_vs_c128(q):
+def test_haar_pairs32_c64_vs_c128(q):
     """32-qubit Haar-pairs circuit (10 layers) in complex128 (64 GiB) and
     complex64 (32 GiB): infidelity of the complex64 state, norm, and the
     circuit followed by its inverse; the same structure at 28 qubits too."""
@@ -146,13 +146,13 @@ def test_config3_32_qubits_c64_vs_c128(q):
     ctx.close()
 
 
-def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
+def test_brick28_full_state_vs_oracle(q, ctx):
     """The 28-qubit brick circuit (20 layers, 1100 gates) in the benchmark's
     launch configuration against the FP64 oracle run on the host over the
     whole 2^28-amplitude state (about 16 GiB of host memory and under a
     minute on 16 cores), amplitude by amplitude; the complex64 run against
     the same state by infidelity."""
-    c = W.config2()
+    c = W.brick_n28()
     st = q.State(ctx, c.n)
     st.init_basis(0)
     st.apply_circuit(c.gates)
@@ -177,7 +177,7 @@ def test_config2_28_qubits_full_state_vs_oracle(q, ctx):
     assert inf <= 1e-6
 
 
-def test_config3_28_qubits_full_state_vs_oracle(q):
+def test_haar_pairs28_full_state_vs_oracle(q):
     """The Haar-pairs circuit at 28 qubits (10 layers, 420 gates: 2-qubit
     gates on random pairs across every bit, the planner's hardest case)
     against the FP64 oracle over the whole state: complex128 with the

@@ -135,8 +135,8 @@ def test_pairings_match_paper_index_maps(q, ctx):
 
 # ------------------------------------------------------------- circuits
 @pytest.mark.parametrize("flags", [0, 1])
-def test_config1_state_and_z(q, ctx, flags):
-    c = W.config1()
+def test_mix10_state_and_z(q, ctx, flags):
+    c = W.mix_n10_g200()
     st = make_state(q, ctx, c.n)
     st.apply_circuit(c.gates, flags=flags)
     ref = O.run(c)

@@ -127,7 +127,7 @@ def test_planner_fuses_layered_circuit():
 
 
 def test_planner_small_state_single_pass():
-    c = W.config1()       # n = 10 <= tile bits: the whole circuit is one pass
+    c = W.mix_n10_g200()       # n = 10 <= tile bits: the whole circuit is one pass
     pog, order, pq = _check_plan(c, 0, 0)
     assert len(pq) == 1 and np.all(pog == 0)
     re = W.Circuit(c.n, [c.gates[i] for i in order])
@@ -179,7 +179,7 @@ def _records_to_circuit(n, recs):
     lambda: W.layered_haar_pairs(15, 4, seed=7),
     lambda: W.hea_cz_ring(13, 3, seed=8),
     lambda: W.qft(12),
-    lambda: W.config1(),
+    lambda: W.mix_n10_g200(),
     lambda: W.random_multicontrol(13, 150, seed=9),
 ])
 @pytest.mark.parametrize("dtype,tb,lb", [(q.QSV_C128, 0, 0), (q.QSV_C128, 10, 2), (q.QSV_C64, 12, 4),

@@ -350,7 +350,7 @@ def test_run_matches_kron_product():
 
 
 def test_inverse_circuit_returns_state():
-    c = W.config1()
+    c = W.mix_n10_g200()
     phi = _rand_state(c.n, 14)
     s = O.run(W.inverse(c), O.run(c, phi))
     assert np.max(np.abs(s - phi)) < 1e-12
@@ -393,7 +393,7 @@ def test_norm_inner_prob_vs_numpy():
 
 
 def test_norm_preserved_by_circuit():
-    c = W.config1()
+    c = W.mix_n10_g200()
     assert abs(O.norm2(O.run(c)) - 1.0) < 1e-13
 
 

@@ -189,9 +189,9 @@ def random_multicontrol(n: int, ngates: int, seed: int, max_controls: int = 3,
     return Circuit(n, gates, np.zeros(0), obs, f"{name}_n{n}_g{ngates}")
 
 
-def config1(seed: int = 1001) -> Circuit:
+def mix_n10_g200(seed: int = 1001) -> Circuit:
     """10 qubits, 200 gates of the 50/25/25 mix; observables <Z_i> for all i."""
-    return random_mix(10, 200, seed, "config1_mix_n10_g200")
+    return random_mix(10, 200, seed, "mix_n10_g200")
 
 
 def layered_cnot_brick(n: int, layers: int, seed: int) -> Circuit:
@@ -211,7 +211,7 @@ def layered_cnot_brick(n: int, layers: int, seed: int) -> Circuit:
     return Circuit(n, gates, np.zeros(0), obs, f"layered_cnot_brick_n{n}_l{layers}")
 
 
-def config2(n: int = 28, layers: int = 20, seed: int = 1002) -> Circuit:
+def brick_n28(n: int = 28, layers: int = 20, seed: int = 1002) -> Circuit:
     return layered_cnot_brick(n, layers, seed)
 
 
@@ -231,7 +231,7 @@ def layered_haar_pairs(n: int, layers: int, seed: int) -> Circuit:
     return Circuit(n, gates, np.zeros(0), obs, f"layered_haar_pairs_n{n}_l{layers}")
 
 
-def config3(n: int = 32, layers: int = 10, seed: int = 1003) -> Circuit:
+def haar_pairs_n32(n: int = 32, layers: int = 10, seed: int = 1003) -> Circuit:
     return layered_haar_pairs(n, layers, seed)
 
 
@@ -254,7 +254,7 @@ def ry_rz_cnot_ladder(n: int, layers: int, rng: np.random.Generator,
     return Circuit(n, gates, np.asarray(params, dtype=np.float64), obs, name)
 
 
-def config4(nb: int = 256, layers: int = 6, nmin: int = 12, nmax: int = 20,
+def ladder_batch_256(nb: int = 256, layers: int = 6, nmin: int = 12, nmax: int = 20,
             seed_base: int = 4000) -> List[Circuit]:
     """Batch of parametrised circuits; circuit b draws its qubit count and
     angles from default_rng(seed_base + b)."""
@@ -293,7 +293,7 @@ def hea_cz_ring(n: int, layers: int, seed: int, ring_obs: bool = False) -> Circu
                    f"hea_cz_ring_n{n}_l{layers}")
 
 
-def config5(n: int = 24, layers: int = 10, seed: int = 1005) -> Circuit:
+def hea_n24(n: int = 24, layers: int = 10, seed: int = 1005) -> Circuit:
     return hea_cz_ring(n, layers, seed)
 
 

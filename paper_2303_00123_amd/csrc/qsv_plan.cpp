@@ -90,8 +90,12 @@ static size_t closure_count(const std::vector<int>& rem, size_t lim, const std::
 // pass takes the most gates (ties: fewer new bits, then circuit order),
 // until no gate's bits fit in the K positions.  This looks past the first
 // gates in circuit order, which an in-order greedy fill would commit to.
-// remaining gate count below which the planner searches the tail
+// remaining gate count below which the planner searches the tail; a second
+// plan that searches from further back (kTailLookGatesWide) is kept only if
+// it needs fewer passes (a plan of the same count can run slower, since its
+// passes carry different gates)
 constexpr size_t kTailLookGates = 400;
+constexpr size_t kTailLookGatesWide = 1000;
 
 static uint64_t choose_bits(const std::vector<int>& rem, const std::vector<uint64_t>& masks, uint64_t S, int K) {
     const size_t lim = std::min(rem.size(), size_t(4096));
@@ -627,7 +631,8 @@ static uint64_t choose_bits_tail(const std::vector<int>& rem, const std::vector<
     return best;
 }
 
-std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {
+static std::vector<Pass> plan_passes_tail(int n, const std::vector<PGate>& gates, const TileConfig& cfg,
+                                          size_t tail_gates) {
     std::vector<Pass> passes;
     std::vector<uint64_t> masks(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) masks[i] = gate_mask(gates[i], n);
@@ -660,7 +665,7 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
         }
         const uint64_t low = (uint64_t(1) << L) - 1;
         uint64_t S = choose_bits(rem, masks, low, K);
-        if (rem.size() <= kTailLookGates) S = choose_bits_tail(rem, masks, low, K, S);
+        if (rem.size() <= tail_gates) S = choose_bits_tail(rem, masks, low, K, S);
         std::vector<int> take, defer;
         take.reserve(rem.size());
         greedy(rem, masks, S, K, true, take, defer);
@@ -686,6 +691,15 @@ std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const Tile
         if (!ps.single) plan_stages(n, gates, ps);
         passes.push_back(std::move(ps));
         rem.swap(defer);
+    }
+    return passes;
+}
+
+std::vector<Pass> plan_passes(int n, const std::vector<PGate>& gates, const TileConfig& cfg) {
+    std::vector<Pass> passes = plan_passes_tail(n, gates, cfg, kTailLookGates);
+    if (gates.size() > kTailLookGates && passes.size() > 2) {
+        std::vector<Pass> wide = plan_passes_tail(n, gates, cfg, kTailLookGatesWide);
+        if (wide.size() < passes.size()) passes = std::move(wide);
     }
     return passes;
 }

@@ -229,16 +229,17 @@ bool read_file(const std::string& path, std::string& out) {
 
 // Resource usage of the compiled kernel from the compiler's remarks: true
 // if it keeps two waves per SIMD and spills at most a few registers to
-// scratch memory (QSV_JIT_MAX_SCRATCH bytes per lane, default 64: passes
+// scratch memory (QSV_JIT_MAX_SCRATCH bytes per lane, default 128: passes
 // full of dense 2-qubit gates, whose 16 complex entries compete with the
-// amplitudes for registers, spill a handful of values).
+// amplitudes for registers, spill a handful of values, and such a kernel
+// still runs well ahead of the interpreting one).
 bool resources_ok(const std::string& log) {
     auto field = [&](const char* key) {
         const size_t p = log.find(key);
         if (p == std::string::npos) return -1;
         return std::atoi(log.c_str() + p + std::strlen(key));
     };
-    int max_scratch = 64;
+    int max_scratch = 128;
     if (const char* m = std::getenv("QSV_JIT_MAX_SCRATCH")) max_scratch = std::atoi(m);
     const int scratch = field("ScratchSize [bytes/lane]: ");
     const int occ = field("Occupancy [waves/SIMD]: ");

@@ -17,8 +17,9 @@
 // Stage 0 uses the load mapping (register bits = the k-8 highest local
 // bits, thread bits = the 8 lowest, which keeps global accesses
 // coalesced); later stages re-map through LDS; the last stage again uses
-// the load mapping so the store is coalesced.  The same greedy, blocking
-// rule orders gates across stages.
+// the load mapping so the store is coalesced.  The same blocking rule
+// orders gates across stages, and a stage's register bits are chosen the way
+// a pass's bits are (the addition that lets the stage take the most gates).
 #include <algorithm>
 #include <complex>
 #include <cstring>
@@ -201,9 +202,18 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         }
     };
 
+    // The bits of each stage are chosen the way a pass chooses its bits
+    // (choose_bits: the addition after which the stage takes the most gates),
+    // not by an in-order fill, which commits to the first gates' bits and
+    // leaves more stages -- and LDS exchanges -- per pass.  For the first
+    // stage, gates on lane bits get bits no register set can hold.
+    constexpr uint64_t kNoFit = ~uint64_t(0) << 48;   // 16 bits above every local bit
+    std::vector<uint64_t> lm0(lm);
+    for (int gi : ps.gates)
+        if (lm[size_t(gi)] & lanes) lm0[size_t(gi)] |= kNoFit;
     ps.stages.clear();
     std::vector<int> rem = ps.gates, take, defer;
-    uint64_t S = 0;
+    uint64_t S = choose_bits(rem, lm0, 0, RB);
     greedy_avoid(rem, S, take, defer);
     ps.stages.push_back(make_stage(S, true, 0, std::move(take)));
     rem.swap(defer);
@@ -211,13 +221,13 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         const uint64_t prev = mask_of(ps.stages.back());
         take.clear();
         defer.clear();
-        S = 0;
+        S = choose_bits(rem, lm, 0, RB);
         greedy(rem, lm, S, RB, false, take, defer);
         if (split && !(S & prev) && __builtin_popcountll(S) == RB) {
             // leave room for a bit shared with the previous stage
             take.clear();
             defer.clear();
-            S = 0;
+            S = choose_bits(rem, lm, 0, RB - 1);
             greedy(rem, lm, S, RB - 1, false, take, defer);
         }
         uint64_t used = 0;

@@ -224,11 +224,25 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         S = choose_bits(rem, lm, 0, RB);
         greedy(rem, lm, S, RB, false, take, defer);
         if (split && !(S & prev) && __builtin_popcountll(S) == RB) {
-            // leave room for a bit shared with the previous stage
+            // a bit shared with the previous stage is needed: leave room for
+            // one, or start the search from one of the previous stage's bits
+            // (then gates on it join for free), whichever takes more gates
             take.clear();
             defer.clear();
             S = choose_bits(rem, lm, 0, RB - 1);
             greedy(rem, lm, S, RB - 1, false, take, defer);
+            std::vector<int> t2, d2;
+            for (uint64_t pb = prev; pb; pb &= pb - 1) {
+                uint64_t S2 = choose_bits(rem, lm, pb & (~pb + 1), RB);
+                t2.clear();
+                d2.clear();
+                greedy(rem, lm, S2, RB, false, t2, d2);
+                if (t2.size() > take.size()) {
+                    S = S2;
+                    take.swap(t2);
+                    defer.swap(d2);
+                }
+            }
         }
         uint64_t used = 0;
         for (int gi : take) used |= lm[size_t(gi)];
@@ -238,7 +252,48 @@ static void plan_stages(int n, const std::vector<PGate>& gates, Pass& ps) {
         ps.stages.push_back(make_stage(S, avoid, prev, std::move(take)));
         rem.swap(defer);
     }
-    // the store needs a stage that keeps the lane bits on lanes
+    // The store needs a stage that keeps the lane bits on lanes.  If the last
+    // stage uses them, try to re-split the gates of the last two stages so
+    // that the gates on lane bits all run in the first of the two and the
+    // second avoids the lanes: that saves the empty store stage (one LDS
+    // exchange).  The gates keep their order and the blocking rule, as in
+    // every stage.
+    const size_t ns = ps.stages.size();
+    if (ns >= 3 && (mask_of(ps.stages.back()) & lanes)) {
+        std::vector<int> G = ps.stages[ns - 2].gates;
+        G.insert(G.end(), ps.stages[ns - 1].gates.begin(), ps.stages[ns - 1].gates.end());
+        const uint64_t prevA = mask_of(ps.stages[ns - 3]);
+        uint64_t seed = 0;
+        for (int gi : G)
+            if (lm[size_t(gi)] & lanes) seed |= lm[size_t(gi)];
+        if (__builtin_popcountll(seed) <= RB) {
+            uint64_t SA = choose_bits(G, lm, seed, RB);
+            std::vector<int> ta, da;
+            greedy(G, lm, SA, RB, false, ta, da);
+            bool ok = (SA & seed) == seed && !(split && !(SA & prevA) && __builtin_popcountll(SA) == RB);
+            uint64_t SB = 0;
+            for (int gi : da) {
+                ok &= !(lm[size_t(gi)] & lanes);
+                SB |= lm[size_t(gi)];
+            }
+            ok &= __builtin_popcountll(SB) <= RB;
+            if (ok) {
+                uint64_t usedA = 0;
+                for (int gi : ta) usedA |= lm[size_t(gi)];
+                Stage A = make_stage(SA, (usedA & lanes) == 0, prevA, std::move(ta));
+                const uint64_t mA = mask_of(A);
+                // B shares a bit with A that is off the lanes (B holds no lane bit)
+                ok = !(split && ((!(SB & mA) && __builtin_popcountll(SB) == RB) || !(mA & ~lanes)));
+                if (ok) {
+                    Stage B = make_stage(SB, true, mA, std::move(da));
+                    if (!(mask_of(B) & lanes)) {
+                        ps.stages[ns - 2] = std::move(A);
+                        ps.stages[ns - 1] = std::move(B);
+                    }
+                }
+            }
+        }
+    }
     if (mask_of(ps.stages.back()) & lanes) {
         uint64_t prev = mask_of(ps.stages.back());
         if (split && !(prev & ~lanes)) {

@@ -397,9 +397,12 @@ qsv_status qsv_plan_fused(int n, int dtype, const qsv_gate* g, int64_t ng, const
                           int64_t nparams, int tile_bits, int low_bits, int reg_bits, int lds_rounds,
                           qsv_gate* out, int64_t cap, int32_t* pass_of_out, int64_t* nout);
 
-/* Host-only query of the fusion plan qsv_apply_circuit would use for an
- * n-qubit circuit (no device work; needs no GPU).  tile_bits / low_bits as in
- * qsv_set_tile (0 = defaults for dtype).  Outputs, each an array of at least
+/* Host-only query of how the pass planner groups the gates of an n-qubit
+ * circuit, taken one to one as given (no device work; needs no GPU), so that
+ * every input gate gets a pass.  qsv_apply_circuit first merges neighbouring
+ * gates by its cost-aware fusion and plans the merged list, which can need
+ * fewer passes; qsv_plan_fused returns exactly what it runs.  tile_bits /
+ * low_bits as in qsv_set_tile (0 = defaults for dtype).  Outputs, each an array of at least
  * ng entries: pass_of_gate[i] = pass that applies gate i; exec_order = gate
  * indices in the order the kernels apply them (passes in sequence; inside a
  * pass, its register stages in sequence); pass_qubits[p] = qubit mask (bit q = qubit q)

@@ -385,7 +385,8 @@ class State:
 
 def plan_circuit(n: int, gates, dtype: int = QSV_C128, tile_bits: int = 0, low_bits: int = 0,
                  reg_bits: int = 0):
-    """Host-only fusion plan: (pass_of_gate, exec_order, pass_qubit_masks)."""
+    """Host-only pass plan of the gates as given, one to one (see
+    qsv_plan_circuit): (pass_of_gate, exec_order, pass_qubit_masks)."""
     g = marshal_gates(gates)
     ng = len(g)
     pog = np.zeros(max(ng, 1), dtype=np.int32)

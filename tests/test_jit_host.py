@@ -50,3 +50,18 @@ def test_generated_source_compiles_without_spills(tmp_path, dtype):
     scratch = int(re.search(r"ScratchSize \[bytes/lane\]: (\d+)", r.stderr).group(1))
     occ = int(re.search(r"Occupancy \[waves/SIMD\]: (\d+)", r.stderr).group(1))
     assert scratch <= 64 and occ >= 2
+
+
+def test_stage_search_keeps_lds_exchanges_low():
+    """Register stages take their bits by search (the addition after which
+    the stage holds the most gates), not by an in-order fill, and the last
+    two stages are re-split so that no empty store stage is needed: on the
+    30-qubit brick the 20 passes need at most 364 LDS barriers (4 per split
+    stage change, 3 for the first); an in-order fill needed 464."""
+    c = W.layered_cnot_brick(30, 20, seed=3002)
+    recs, pas = q.plan_fused(c.n, c.gates, c.params, q.QSV_C128)
+    npass = int(pas.max()) + 1
+    assert npass == 20
+    barriers = sum(q.jit_source(c.n, c.gates, p, params=c.params).count("lds_barrier")
+                   for p in range(npass))
+    assert barriers <= 364

@@ -300,16 +300,16 @@ __global__ __launch_bounds__(kThreads) void k_adj_cols(const double* __restrict_
 }
 
 // Two-vector tile shape per precision (measured on a 24-qubit, 480-angle
-// circuit).  complex128: 2^11 amplitudes with split exchange, 32 KiB of LDS
-// and about 135 registers, so three workgroups fit per CU.  complex64: 2^12
-// amplitudes with full exchange (64 KiB, two per CU); its split variant
-// is no faster, being register-bound at two waves per SIMD either way.
-// The axis-specialised rotation bodies push the complex64 kernel past 256
-// registers (one wave per SIMD), so it keeps the generic 2x2 body.
+// circuit): 2^11 amplitudes with split exchange for both.  complex128: 32 KiB
+// of LDS and about 135 registers, three workgroups per CU.  complex64: 16 KiB
+// and about 100 registers with the generic 2x2 rotation body, four waves per
+// SIMD; the axis-specialised bodies take it to 132 registers (three waves)
+// and 2^12 tiles with full exchange to 200 (two), both slower (adjoint sweep
+// 9.67 and 9.88 ms against 9.50).
 template <typename R>
 struct AdjShape {
-    static constexpr int K = sizeof(R) == 8 ? 11 : 12;
-    static constexpr bool SPLIT = sizeof(R) == 8;
+    static constexpr int K = 11;
+    static constexpr bool SPLIT = true;
     static constexpr bool SPEC = sizeof(R) == 8;
 };
 
